@@ -1,0 +1,249 @@
+"""Benchmark of the converted-view SPH step on one MI355X.
+
+One step = cells_build, the density view (gather, density with the
+smoothing-length iteration, scatter), the force view (gather, force, time-step
+and conservation reduction, scatter) and kick_drift, all through the C-ABI on
+one stream.  The workload is the two-state tube: a 64^3 lattice (density 1,
+pressure 1) beside a 32^3 lattice (density 1/8, pressure 0.1) in the periodic
+box [0,2]x[0,1]^2, 294,912 particles in 256-byte records, FP64.
+
+value = (density pairs + force pairs) per second over the timed steps, the pairs
+counted by the kernels themselves (j != i inside the support at the accepted h).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic flops per true pair (FMA = 2, sqrt and division = 1 each), counted
+# on the pair formulas of the density and force loops
+FLOPS_DENSITY_PAIR = 26
+FLOPS_FORCE_PAIR = 67
+PEAK_FP64_VALU = 256 * 2.4e9 * 128          # 256 CUs x 2.4 GHz x 64 FMA lanes: 78.6 TFLOP/s
+PEAK_FP32_VALU = 157.3e12                   # published, needs packed FP32
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_stepper(torch, sv, inputs, w, precision, lay):
+    p = sv.params_for(w)
+    if precision == sv.PREC_FP32:
+        p.h_tol = 1e-6
+    st = sv.Stepper(w.rec, p, precision, layout_density=lay, layout_force=lay,
+                    stream=torch.cuda.current_stream())
+    return st
+
+
+def run_timed(torch, sv, st, steps, warmup, graph=False):
+    """Warm up, then time exactly `steps` steps; per-kernel HIP events around
+    the density and force pair loops on the same stream."""
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        st.step()
+    torch.cuda.synchronize()
+    g = None
+    if graph:
+        sv.graph_begin(s)
+        st.step()
+        g = sv.graph_end(s)
+        torch.cuda.synchronize()
+    before = st.read_state()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_start.record(s)
+    for k in range(steps):
+        if graph:
+            sv.graph_launch(g, s)
+            continue
+        sv.begin_step(st.state, s)
+        sv.cells_build(st.cells, st.aos, st.d_cells, st.state, s)
+        sv.aos_to_soa(st.v_dens, st.cells, s)
+        ev[k][0].record(s)
+        sv.sph_density(st.v_dens, st.cells, st.p, st.state, s)
+        ev[k][1].record(s)
+        sv.soa_to_aos(st.v_dens, s)
+        sv.aos_to_soa(st.v_force, st.cells, s)
+        ev[k][2].record(s)
+        sv.sph_force(st.v_force, st.cells, st.p, st.state, s)
+        ev[k][3].record(s)
+        sv.step_reduce(st.v_force, st.p, st.state, s)
+        sv.soa_to_aos(st.v_force, s)
+        sv.kick_drift(st.aos, st.d_kick, st.n, st.p, st.state, s)
+    e_end.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    after = st.read_state()
+    ms = e_start.elapsed_time(e_end)
+    res = dict(ms_total=ms, wall_s=wall, pairs=after.pairs_total - before.pairs_total,
+               flags=after.flags, state=after)
+    if not graph:
+        res["ms_density"] = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+        res["ms_force"] = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+    if g is not None:
+        sv.graph_destroy(g)
+    return res
+
+
+def pair_evals_per_step(torch, sv, st):
+    """One more (untimed) step to read the per-step pair counters."""
+    st.step()
+    s = st.read_state()
+    return s.pair_evals_density, s.pairs_force, s.pairs_density
+
+
+def cpu_baseline(inputs, w):
+    """The oracle (plain scalar C, OpenMP over its target particles, all host
+    threads) on one step of the same workload: density with the h iteration
+    for every particle, then the force for every particle from the oracle's own
+    density.  On this workload that is about 10 s of CPU work."""
+    import numpy as np
+
+    from oracle import oracle as orc
+
+    S = inputs.SLOT
+    rec = w.rec
+    box = orc.box_of(w.lo, w.length, w.periodic)
+    c = {k: np.ascontiguousarray(rec[:, S[k]]) for k in S if k not in inputs.INT_SLOTS}
+    nthreads = orc.max_threads()
+    t0 = time.perf_counter()
+    d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads)
+    t1 = time.perf_counter()
+    f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], d["h"], d["rho"], d["omega"],
+                  c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads)
+    t2 = time.perf_counter()
+    pairs = int(d["count"].sum()) + int(f["count"].sum())
+    cpu = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"one full step of the same {w.n}-particle workload (density with h iteration "
+                      f"{t1 - t0:.2f} s + force {t2 - t1:.2f} s wall, {nthreads} threads, {cpu})",
+            "pairs": pairs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how "
+              "the step would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2502_16517_amd import inputs
+    from paper_2502_16517_amd import sphview as sv
+
+    torch.cuda.set_device(0)
+    # one side stream (default priority) for everything: graph capture needs a
+    # stream other than the legacy null stream, and events record on it
+    torch.cuda.set_stream(torch.cuda.Stream())
+    log("[bench] generating the two-state tube (294,912 particles)")
+    w = inputs.config2()
+    lay = sv.layout(sv.LAYOUT_SOA)
+
+    log("[bench] fp64 eager")
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
+    r64 = run_timed(torch, sv, st, args.steps, args.warmup)
+    evals_d, pairs_f, pairs_d = pair_evals_per_step(torch, sv, st)
+    st.close()
+    if r64["flags"]:
+        log(f"[bench] warning: status flags {r64['flags']:#x}")
+
+    log("[bench] fp64 graph")
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
+    g64 = run_timed(torch, sv, st, args.steps, args.warmup, graph=True)
+    st.close()
+
+    f32 = None
+    if not args.no_fp32:
+        log("[bench] fp32 eager")
+        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP32, lay)
+        r32 = run_timed(torch, sv, st, args.steps, args.warmup)
+        st.close()
+        f32 = {"value": r32["pairs"] / (r32["ms_total"] / 1e3), "ms_per_step": r32["ms_total"] / args.steps,
+               "ms_density": r32["ms_density"], "ms_force": r32["ms_force"],
+               "speedup_vs_fp64": (r32["pairs"] / r32["ms_total"]) / (r64["pairs"] / r64["ms_total"])}
+
+    ms_step = r64["ms_total"] / args.steps
+    value = r64["pairs"] / (r64["ms_total"] / 1e3)
+    # dominant kernel: the larger of the two pair loops
+    dens_flops = evals_d * FLOPS_DENSITY_PAIR
+    force_flops = pairs_f * FLOPS_FORCE_PAIR
+    if r64["ms_force"] >= r64["ms_density"]:
+        kern, flops, ms_k = "force", force_flops, r64["ms_force"]
+    else:
+        kern, flops, ms_k = "density", dens_flops, r64["ms_density"]
+    achieved = flops / (ms_k / 1e3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get(kern)
+    roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop)", "achieved": achieved,
+                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VALU / 1e12),
+                "traffic": traffic,
+                "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12},
+                "force": {"ms": r64["ms_force"], "tflops": force_flops / (r64["ms_force"] / 1e3) / 1e12}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(inputs, w)
+
+    out = {
+        "metric": "pair interactions/s (density+force incl. AoS<->SoA views)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two-state tube 64^3 + 32^3 = 294,912 particles, periodic [0,2]x[0,1]^2, "
+                               "256-byte 32-slot records, SoA views, FP64",
+                   "n": w.n, "grid": list(w.grid), "layout": "soa", "tpi": "auto", "pairs_per_step":
+                       {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "graph": {"value": g64["pairs"] / (g64["ms_total"] / 1e3), "ms_per_step": g64["ms_total"] / args.steps},
+        "fp32": f32,
+        "hbm_frac_step": None,
+    }
+    # whole-step HBM fraction: algorithmic view bytes (gathers, scatters, loop
+    # inputs and outputs) over the step time
+    n = w.n
+    algo_bytes = n * (80 + 64 + 192 + 80) + n * (40 + 32) * max(1, round(evals_d / max(pairs_d, 1))) + n * (96 + 40)
+    out["hbm_frac_step"] = algo_bytes / (ms_step / 1e3) / HBM_PEAK
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

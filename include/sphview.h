@@ -1,0 +1,326 @@
+/*
+ * sphview.h -- C-ABI of libsphview.so: temporary, local AoS-to-SoA views around
+ * SPH particle-interaction kernels, on AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows the paper's formalism (Sec. 4, eq. "view"):
+ * a user array D of N structs (records of a fixed byte stride) and a loop body f
+ * over it are evaluated as
+ *
+ *     f(D) = (W_out o C^T o f_hat o C o N_{in u out}) (D)
+ *
+ * where N narrows each record to the members the loop reads (A_in) or writes
+ * (A_out), C converts AoS to SoA (into explicit storage, Sec. 4.2), f_hat is the
+ * loop over the converted data, C^T converts back and W_out widens only the
+ * written members into the records.  Here:
+ *
+ *   sphv_view_create   plans the explicit storage of one view   (Sec. 3.1)
+ *   sphv_aos_to_soa    N then C: gather of A_in                 (Sec. 3.1 prologue)
+ *   sphv_sph_density   f_hat for the density loop               (Sec. 2.1 step 1)
+ *   sphv_sph_force     f_hat for the force loop                 (Sec. 2.1 step 2)
+ *   sphv_step_reduce   CFL time step and conservation sums      (Sec. 2.1, leapfrog)
+ *   sphv_soa_to_aos   C^T then W: scatter of A_out only        (Sec. 3.1 epilogue)
+ *   sphv_kick_drift    the linear kick / drift / kick updates   (Sec. 2.1 steps 3-5)
+ *
+ * and sphv_cells_build sorts particles into cells (Sec. 2.1, the mesh helper) so
+ * that a local cell's active set is its neighbour cells (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SPHV_OK (0) or a negative SPHV_E_* code; no C++ exception
+ *    crosses this boundary.  sphv_status_string() names a code.
+ *  - "device" pointers are HIP device memory of the current device; the caller
+ *    owns them (AoS, workspaces, state block) and keeps them alive while any
+ *    handle or queued work uses them.  The library never allocates or frees
+ *    device memory; it allocates only small host handles freed by *_destroy.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued asynchronously on it; only sphv_read_state and
+ *    sphv_write_state synchronise with the host.
+ *  - Asynchronous conditions (non-finite input, h iteration not converged, ...)
+ *    set SPHV_F_* bits in the device state block instead of returning errors.
+ */
+#ifndef SPHVIEW_H
+#define SPHVIEW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+
+enum {
+    SPHV_OK = 0,
+    SPHV_E_INVALID_ARG = -1,   /* NULL pointer, negative size, bad enum value        */
+    SPHV_E_DESCRIPTOR = -2,    /* field outside the record, overlap, misaligned,     */
+                               /* unsupported dtype, missing role the loop needs     */
+    SPHV_E_WORKSPACE = -3,     /* workspace too small or misaligned (256 B)          */
+    SPHV_E_ALIAS = -4,         /* another open view on the same records writes what  */
+                               /* this one reads or writes, or vice versa (Sec. 3.3) */
+    SPHV_E_STATE = -5,         /* call out of order (e.g. density before gather)     */
+    SPHV_E_HIP = -6,           /* a HIP runtime call or kernel launch failed         */
+    SPHV_E_UNSUPPORTED = -7    /* valid request this build does not implement       */
+};
+
+/* bits of sphv_state.flags (sticky until sphv_state_init) */
+enum {
+    SPHV_F_NONFINITE_INPUT = 1u << 0,  /* NaN/inf position or h seen by cells_build     */
+    SPHV_F_H_NOT_CONVERGED = 1u << 1,  /* some particle used all max_iter density passes */
+    SPHV_F_H_CAP_HIT = 1u << 2,        /* h wanted to exceed its cell reach: use a     */
+                                       /* coarser grid or a larger headroom            */
+    SPHV_F_QUEUE_OVERFLOW = 1u << 3,   /* work items exceeded the planned capacity      */
+    SPHV_F_NONFINITE_OUTPUT = 1u << 4, /* NaN/inf density or force result               */
+    SPHV_F_GRID_TOO_SMALL = 1u << 5,   /* a reach window wraps onto itself (periodic)   */
+    SPHV_F_OUT_OF_BOX = 1u << 6        /* a particle lies outside an open box           */
+};
+
+const char* sphv_status_string(int32_t status);
+int32_t sphv_version(void);   /* 100 * major + minor */
+
+/* ------------------------------------------------------------ descriptor */
+
+enum { SPHV_F64 = 1, SPHV_F32 = 2, SPHV_I64 = 3, SPHV_I32 = 4 };
+/* A_in only, A_out only, A_in and A_out (one instance in the view, Sec. 3.3) */
+enum { SPHV_IN = 1, SPHV_OUT = 2, SPHV_INOUT = 3 };
+
+/* Role of a member in the SPH loops; SPHV_ROLE_USER for any other member. */
+enum {
+    SPHV_ROLE_USER = 0,
+    SPHV_X, SPHV_Y, SPHV_Z, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_VHX, SPHV_VHY, SPHV_VHZ,
+    SPHV_AX, SPHV_AY, SPHV_AZ, SPHV_M, SPHV_H, SPHV_RHO, SPHV_OMEGA, SPHV_U, SPHV_UH,
+    SPHV_UDT, SPHV_ALPHA, SPHV_VSIG, SPHV_WCOUNT,
+    SPHV_NROLES
+};
+
+/* One struct member: byte offset inside a record, its dtype, whether the loop
+ * reads and/or writes it, and its SPH role. */
+typedef struct {
+    uint64_t offset;
+    uint32_t role;
+    uint16_t dtype;
+    uint16_t access;
+} sphv_field;
+
+/* The records and the members a loop touches.  Record i's member f lives at
+ * base + i*stride + fields[f].offset.  Two storage shapes are accepted:
+ *  - array of structs: every member lies inside the stride (offset+size <= stride);
+ *  - struct of arrays: stride equals the member size and members are whole
+ *    arrays of n elements that do not overlap (offset >= previous + n*size).
+ * Members must be naturally aligned and must not overlap; a role may appear
+ * at most once. */
+typedef struct {
+    uint64_t stride;
+    uint32_t n_fields;
+    uint32_t reserved;
+    const sphv_field* fields;
+} sphv_descriptor;
+
+/* ---------------------------------------------------------------- params */
+
+/* Box, grid and physics constants.  cell[d] = len[d]/grid[d] and
+ * inv_cell[d] = grid[d]/len[d] are filled by sphv_params_init and used as given
+ * (the binning formula below depends on their exact values). */
+typedef struct {
+    double lo[3];
+    double len[3];
+    double cell[3];
+    double inv_cell[3];
+    int32_t grid[3];
+    int32_t periodic[3];
+    double gamma;      /* adiabatic index (5/3)                                  */
+    double eta;        /* density target rho h^3 = m eta^3                        */
+    double cfl;        /* Courant factor of dt = cfl min h / v_sig                */
+    double h_tol;      /* Newton stop |h+ - h| <= h_tol h                         */
+    double headroom;   /* cell reach: R = ceil(2 h headroom / min cell), >= 1     */
+    int32_t max_iter;  /* density passes, 1..64                                   */
+    int32_t reserved;
+} sphv_params;
+
+/* Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16. */
+int32_t sphv_params_init(sphv_params* p, const double lo[3], const double len[3],
+                         const int32_t grid[3], const int32_t periodic[3]);
+
+/* ----------------------------------------------------------- state block */
+
+/* Host mirror of the device state block (sphv_state_bytes() bytes, caller-owned
+ * device memory).  dt is written by sphv_step_reduce (dt_prev keeps the one
+ * before, nstep counts its calls); sums are fixed-order FP64 totals over particles:
+ *   [0..2] sum m v, [3] sum m (|v|^2/2 + u), [4..6] sum m a, [7] sum m (v.a + du/dt)
+ * pairs_* count ordered pairs (i, j != i) inside the support at the accepted h
+ * (density: r < 2 h_i; force: r < 2 max(h_i, h_j)); pair_evals_density counts
+ * such pairs over every density pass that was executed; pairs_total keeps
+ * adding pairs_density and pairs_force over all steps (not reset per step). */
+typedef struct {
+    uint32_t flags;
+    int32_t max_iters;
+    int64_t nstep;
+    double dt;
+    double dt_prev;
+    double t;
+    double sums[8];
+    int64_t pairs_density;
+    int64_t pairs_force;
+    int64_t pair_evals_density;
+    int64_t pairs_total;     /* density + force pairs since sphv_state_init */
+    int64_t reserved[3];
+} sphv_state;
+
+size_t sphv_state_bytes(void);
+/* Zero the whole block (flags, dt history, counters) with a fill kernel. */
+int32_t sphv_state_init(void* state_dev, void* stream);
+/* Zero the per-step pair counters only (a fill kernel; graph-capturable). */
+int32_t sphv_begin_step(void* state_dev, void* stream);
+/* Copy the block to the host; synchronises the stream. */
+int32_t sphv_read_state(const void* state_dev, sphv_state* out, void* stream);
+/* Copy a host block to the device; synchronises the stream. */
+int32_t sphv_write_state(void* state_dev, const sphv_state* in, void* stream);
+
+/* ----------------------------------------------------------------- cells */
+
+/* Uniform linked-cell grid (paper Sec. 2.1: particles sorted into cells so that
+ * only neighbouring cells interact; Sec. 5.2: particles of a cell as one chunk
+ * with CSR-like chunk offsets).
+ *   key_i = (kz ny + ky) nx + kx,  k_d = clamp(floor((x_d - lo_d) * inv_cell_d), 0, n_d - 1)
+ *   perm  = stable sort of i by key (ties keep index order): sorted position -> record
+ *   cell_start[c] .. cell_start[c+1] = the sorted positions of cell c.
+ * A cell's reach R (cells per axis) covers 2 h headroom of its largest h; the
+ * density loop of a particle in cell c visits the (2R+1)^3 cells around c and
+ * its h is capped at R * min(cell) / 2; the force loop widens R to cover
+ * neighbours' supports.  Work items are (cell, first sorted position, count<=64). */
+typedef struct sphv_cells sphv_cells;
+
+typedef struct {
+    const int32_t* perm;        /* [n]          sorted position -> record index   */
+    const int32_t* cell_start;  /* [n_cells+1]                                     */
+    const int32_t* key;         /* [n]          key of record i (unsorted order)   */
+    const int32_t* reach;       /* [2*n_cells]  density reach, then force reach    */
+    int64_t n;
+    int64_t n_cells;
+    int64_t max_items;
+} sphv_cells_info;
+
+size_t sphv_cells_workspace_bytes(int64_t n, const sphv_params* p);
+int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p,
+                          void* ws_dev, size_t ws_bytes);
+/* Bin, sort, offsets, per-cell reach and work items from the records' x, y, z, h
+ * (roles SPHV_X, SPHV_Y, SPHV_Z, SPHV_H of d; any access).  state_dev gets flags. */
+int32_t sphv_cells_build(sphv_cells* c, const void* aos_dev, const sphv_descriptor* d,
+                         void* state_dev, void* stream);
+int32_t sphv_cells_get_info(const sphv_cells* c, sphv_cells_info* out);
+void sphv_cells_destroy(sphv_cells* c);
+
+/* ----------------------------------------------------------------- views */
+
+enum {
+    SPHV_LAYOUT_SOA = 0,     /* one array per member (Sec. 2.4, Listing 2)           */
+    SPHV_LAYOUT_AOSOA = 1,   /* blocks of aosoa_width particles, SoA inside a block  */
+    SPHV_LAYOUT_DIRECT = 2   /* no conversion: loops read and write the records      */
+                             /* through the index (the paper's unconverted kernels)  */
+};
+enum { SPHV_PREC_FP64 = 0, SPHV_PREC_FP32 = 1 };
+
+/* Layout and tile shape of one view and of the pair loops run over it.
+ * tpi: lanes that share one local particle (1..64, 0 = automatic: 64 / count
+ * of the work item).  masked: 1 evaluates every candidate pair and multiplies
+ * out-of-range terms by zero (Sec. 5.6, neutral elements), 0 branches.  Both
+ * give bit-identical results; tpi changes the summation order. */
+typedef struct {
+    uint32_t kind;
+    uint32_t aosoa_width;   /* power of two, 8..1024, for SPHV_LAYOUT_AOSOA */
+    uint32_t tpi;
+    uint32_t masked;
+} sphv_layout;
+
+/* Precision of the view (SPHV_PREC_*):
+ *  FP64: every member is a bit copy of the record's member.
+ *  FP32: members read only (A_in \ A_out) of dtype f64 are stored as float:
+ *        positions relative to the lower corner of their cell,
+ *        float(x - (lo + k * cell)), other members float(v), both rounded to
+ *        nearest even; members written (A_out) stay f64.  The pair loops then
+ *        run in FP32 with compensated FP32 sums; the h iteration's Newton step
+ *        and convergence test stay FP64. */
+typedef struct sphv_view sphv_view;
+
+size_t sphv_view_workspace_bytes(const sphv_descriptor* d, int64_t n, const sphv_layout* l,
+                                 int32_t precision);
+/* Plan a view of n records of aos_dev described by d.  index_dev (device int32[n],
+ * or NULL for 0..n-1) is the loop's container: view element p is record
+ * index_dev[p] (paper Sec. 2.3, the local/active particle lists).  The SPH loops
+ * need the view indexed by the cells' perm.  Host-only: validates and plans the
+ * workspace; enqueues nothing. */
+int32_t sphv_view_create(sphv_view** out, const sphv_descriptor* d, int64_t n,
+                         const sphv_layout* l, int32_t precision, void* aos_dev,
+                         const int32_t* index_dev, void* ws_dev, size_t ws_bytes);
+/* Gather A_in (the prologue).  Opens the view: until sphv_soa_to_aos the
+ * records' members in A_in u A_out are temporarily invalid (Sec. 3.2); other
+ * members stay valid and are never touched.  A_out \ A_in is not initialised
+ * (Sec. 3.1).  cells is required for FP32 views (cell of each element) and may
+ * be NULL otherwise.  Fails with SPHV_E_ALIAS if another open view on
+ * overlapping records writes a member this one touches, or touches a member
+ * this one writes. */
+int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream);
+/* Scatter A_out only (the epilogue) and close the view. */
+int32_t sphv_soa_to_aos(sphv_view* v, void* stream);
+/* Device address, dtype and element stride (bytes between consecutive elements
+ * inside one block; blocks are block_bytes apart, block_len elements each) of
+ * field k of an SoA/AoSoA view, for inspection. */
+int32_t sphv_view_field(const sphv_view* v, uint32_t k, void** dev_ptr, int32_t* dtype,
+                        uint64_t* block_len, uint64_t* block_bytes);
+void sphv_view_destroy(sphv_view* v);
+
+/* Density loop (paper Sec. 2.1 step 1) over an open view indexed by the cells'
+ * perm.  View members: IN x, y, z, m; INOUT h; OUT rho, omega, wcount.
+ * For each particle i, at its current h, over j in its cells' window:
+ *   rho_i = sum_j m_j W(r_ij, h), drho_i/dh = sum_j m_j dW/dh, n_i = sum_j W
+ * (j = i included), W the cubic M4 spline with support 2h; then a Newton step
+ * on rho_i(h) h^3 = m_i eta^3, h+ = h - f/f', f' = drho/dh + 3 m eta^3/h^4,
+ * clamped to [h/2, 2h] and to the cell cap (fixed point eta (m/rho)^(1/3) if
+ * f' <= 0).  The current h is accepted when |h+ - h| <= h_tol h, else h = h+
+ * and the sums are redone, at most max_iter times.  Outputs at the accepted h:
+ * rho, omega = 1 + h/(3 rho) drho/dh, wcount = (4 pi/3)(2h)^3 n. */
+int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p,
+                         void* state_dev, void* stream);
+/* Force loop (paper Sec. 2.1 step 2) over an open view indexed by the cells'
+ * perm.  View members: IN x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha;
+ * OUT ax, ay, az, u_dt, v_sig.  Pairs j != i with r < 2 max(h_i, h_j):
+ *   P = (gamma-1) rho u, c = sqrt(gamma (gamma-1) u), A = P/(omega rho^2),
+ *   g = dW/dr(r, h) per side, gbar = (g_i + g_j)/2, w = v_ij . r_hat,
+ *   mu = min(w, 0), v_sig,ij = c_i + c_j - 3 mu,
+ *   Pi = -(alpha_i + alpha_j)/4 v_sig,ij mu / ((rho_i + rho_j)/2),
+ *   a_i  -= m_j (A_i g_i + A_j g_j + Pi gbar) r_hat
+ *   u_dt += m_j (A_i g_i + Pi gbar / 2) w,   v_sig,i = max(2 c_i, max_j v_sig,ij). */
+int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p,
+                       void* state_dev, void* stream);
+/* Time-step reduction over an open force view after sphv_sph_force: in one
+ * fixed-order FP64 tree (deterministic), dt = cfl min_i h_i / v_sig,i (the
+ * division rounded per particle) and the conservation sums of sphv_state.
+ * Updates the state block: t += old dt, dt_prev = old dt, dt = new dt,
+ * nstep += 1.  Inputs m, v, u, h are read from the records (members a view
+ * only reads are never modified while it is open), outputs from the view. */
+int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state_dev, void* stream);
+
+/* Kick / drift / kick with prediction (paper Sec. 2.1 steps 3-5) on the records
+ * directly (linear loop, no view), every product and sum rounded on its own:
+ *   if nstep > 1: v = vh + a (dt_prev/2), u = uh + u_dt (dt_prev/2)   (close step)
+ *   vh = v + a (dt/2), uh = u + u_dt (dt/2)                           (open step)
+ *   x = x + vh dt, wrapped once into [lo, lo+len) on periodic axes     (drift)
+ *   v = vh + a (dt/2), u = uh + u_dt (dt/2)                           (predict)
+ * dt, dt_prev and nstep are read from the device state block.  Members: x, y, z,
+ * vx, vy, vz, vhx, vhy, vhz, ax, ay, az, u, uh, u_dt. */
+int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
+                        const sphv_params* p, const void* state_dev, void* stream);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Capture everything enqueued on stream between begin and end into a HIP graph
+ * (thread-local capture mode); launch replays it on any stream. */
+typedef struct sphv_graph sphv_graph;
+int32_t sphv_graph_begin(void* stream);
+int32_t sphv_graph_end(void* stream, sphv_graph** out);
+int32_t sphv_graph_launch(sphv_graph* g, void* stream);
+void sphv_graph_destroy(sphv_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHVIEW_H */

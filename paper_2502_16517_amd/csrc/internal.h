@@ -1,0 +1,139 @@
+// Internal declarations shared by the host ABI layer and the HIP kernels of
+// libsphview.so.  Not installed; the public contract is include/sphview.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sphview.h"
+
+namespace sphv {
+
+constexpr int kMaxFields = 32;
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kRedBlock = 1024;  // particles per block of the fixed-order reductions
+
+// Device state block (mirrors sphv_state field for field).
+struct DevState {
+    uint32_t flags;
+    int32_t max_iters;
+    int64_t nstep;
+    double dt;
+    double dt_prev;
+    double t;
+    double sums[8];
+    unsigned long long pairs_density;
+    unsigned long long pairs_force;
+    unsigned long long pair_evals_density;
+    unsigned long long pairs_total;
+    int64_t reserved[3];
+};
+static_assert(sizeof(DevState) == sizeof(sphv_state), "state mirror");
+
+// Where element p of one field lives.
+//  view (SoA / AoSoA): base + off + (p >> lw) * block_bytes + (p & mask) * size
+//  direct (records):   base + off + index[p] * stride
+struct FieldRef {
+    char* base;
+    uint64_t off;
+    uint32_t size;     // bytes of one element
+    uint32_t dtype;    // storage dtype (SPHV_F64 / F32 / I64 / I32)
+    int32_t rel_axis;  // >= 0: FP32 cell-relative coordinate along this axis
+    int32_t pad;
+};
+
+struct Access {
+    uint32_t lw;          // log2 block length (view); 63 for plain SoA
+    uint32_t pad;
+    uint64_t mask;        // block length - 1 (view); all ones for plain SoA
+    uint64_t block_bytes; // view
+    const int32_t* index; // direct
+    uint64_t stride;      // direct
+};
+
+// Grid geometry passed to kernels.
+struct Geom {
+    double lo[3], len[3], cell[3], inv_cell[3];
+    int32_t n[3], periodic[3];
+    double cmin;      // min cell edge
+    double headroom;
+};
+
+struct CellsDev {
+    int32_t* key;          // [n] key of record i
+    int32_t* perm;         // [n]
+    int32_t* perm_tmp;     // [n] cell-grouped, not yet ordered within a cell
+    int32_t* key_sorted;   // [n] cell of sorted position p
+    int32_t* cell_start;   // [nc + 1]
+    int32_t* counts;       // [nc]
+    int32_t* cursor;       // [nc]
+    uint32_t* hmax_bits;   // [nc] float bits of 2 h headroom max
+    int32_t* reach_d;      // [nc]
+    int32_t* reach_f;      // [nc]
+    int32_t* tmp_a;        // [nc] scratch for the reach filter / item counts
+    int32_t* tmp_b;        // [nc]
+    int32_t* item_start;   // [nc + 1]
+    int4* items;           // [max_items]  (cell, first sorted pos, count, 0)
+    int32_t* scan_part;    // [scan blocks + 1]
+    int32_t* meta;         // [64]: 0 n_items, 1 R_global, 2.. queue heads/exits
+    int64_t n;
+    int64_t nc;
+    int64_t max_items;
+};
+
+// meta[] slots
+enum {
+    META_NITEMS = 0,
+    META_RGLOBAL = 1,
+    META_QHEAD_D = 8,    // 8 per-XCD heads for the density queue
+    META_QEXIT_D = 16,
+    META_QHEAD_F = 24,
+    META_QEXIT_F = 32,
+    META_SIZE = 64
+};
+
+// Arguments of the pair kernels.
+struct PairArgs {
+    FieldRef f[SPHV_NROLES];   // by role (only the loop's roles are filled)
+    Access acc;
+    Geom g;
+    const int4* items;
+    const int32_t* cell_start;
+    const int32_t* reach;      // density or force reach
+    const int32_t* key_sorted; // cell of sorted position p
+    int32_t* meta;             // queue counters
+    int32_t qhead, qexit;      // meta slots of this kernel's queue
+    DevState* state;
+    double eta, tol, gamma;
+    int32_t max_iter;
+    int32_t tpi;               // 0 = automatic
+    int32_t nblocks;           // grid size (for the exit counter)
+    int32_t pad;
+    double* red_part;          // force: per reduction block partials
+    int64_t n;
+    double cfl;
+};
+
+}  // namespace sphv
+
+// launchers (defined in the .hip files), return hipError_t
+namespace sphv {
+hipError_t launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_state_init(DevState* st, int full, hipStream_t s);
+hipError_t launch_cells_build(const CellsDev& c, const FieldRef* xyzh, const Access& rec,
+                              const Geom& g, DevState* st, hipStream_t s);
+hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
+                         const Access& dst_acc, const int32_t* cell_key, const Geom& g, int64_t n,
+                         hipStream_t s);
+hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
+                          const Access& dst_acc, int64_t n, hipStream_t s);
+hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s);
+hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s);
+hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
+                               const Access& outacc, int out_direct, DevState* st, double cfl, int64_t n,
+                               double* partials, hipStream_t s);
+hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g,
+                             const DevState* st, int64_t n, hipStream_t s);
+int pair_grid_blocks(int64_t max_items);
+}  // namespace sphv

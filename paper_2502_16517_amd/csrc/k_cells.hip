@@ -1,0 +1,348 @@
+// Cell binning, stable counting sort into cells, per-cell reach and the work
+// items of the pair loops (paper Sec. 2.1: particles are sorted into cells so
+// that only neighbouring cells interact; Sec. 5.2: the particles of one cell
+// form one chunk, indexed by CSR-like offsets).
+//
+// Pipeline (all on one stream, no host synchronisation):
+//   fill        counts, hmax, meta := 0
+//   bin         key_i, counts[key]++, hmax[key] = max 2 h headroom, flags
+//   scan        cell_start = exclusive scan of counts, cursor = cell_start
+//   place       perm_tmp[cursor[key_i]++] = i       (cell-grouped, any order)
+//   segsort     perm[cell] = ascending record indices of the cell: the stable
+//               order (ties by index), key_sorted, reach_d, item counts
+//   scan        item_start; n_items
+//   items       (cell, first, count <= 64) per 64 particles of a cell
+//   reach_f     separable box max of reach_d over +-R_global cells
+#include "k_common.h"
+
+namespace sphv {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 1024 elements per block
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_state_init(DevState* st, int full)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (full) {
+        uint32_t* w = (uint32_t*)st;
+        for (size_t k = 0; k < sizeof(DevState) / 4; ++k) w[k] = 0u;
+        return;
+    }
+    st->pairs_density = 0ull;
+    st->pairs_force = 0ull;
+    st->pair_evals_density = 0ull;
+    st->max_iters = 0;
+}
+
+__global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,
+                      uint64_t stride, Geom g, int64_t n, int32_t* key, int32_t* counts,
+                      uint32_t* hmax_bits, DevState* st)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t rb = (uint64_t)i * stride;
+    double c[3];
+    c[0] = *(const double*)(fx.base + fx.off + rb);
+    c[1] = *(const double*)(fy.base + fy.off + rb);
+    c[2] = *(const double*)(fz.base + fz.off + rb);
+    double h = *(const double*)(fh.base + fh.off + rb);
+    bool finite = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]);
+    int k[3];
+    bool outside = false;
+    for (int d = 0; d < 3; ++d) {
+        // k_d = clamp(floor((x_d - lo_d) * inv_cell_d), 0, n_d - 1), each step rounded
+        double t = floor(__dmul_rn(__dsub_rn(c[d], g.lo[d]), g.inv_cell[d]));
+        if (!isfinite(t)) t = 0.0;
+        if (t < 0.0) { t = 0.0; outside = true; }
+        if (t > (double)(g.n[d] - 1)) { t = (double)(g.n[d] - 1); outside = true; }
+        k[d] = (int)t;
+    }
+    int kk = finite ? cell_key(k[0], k[1], k[2], g) : 0;
+    key[i] = kk;
+    atomicAdd(&counts[kk], 1);
+    // support radius with headroom; positive floats order like their bits
+    float H = __double2float_ru(2.0 * h * g.headroom);
+    if (!(isfinite(h) && h > 0.0)) {
+        set_flag(st, SPHV_F_NONFINITE_INPUT);
+        H = 0.0f;
+    }
+    atomicMax(&hmax_bits[kk], __float_as_uint(H));
+    if (!finite) set_flag(st, SPHV_F_NONFINITE_INPUT);
+    bool open_out = false;
+    for (int d = 0; d < 3; ++d) open_out |= (!g.periodic[d] && outside);
+    if (finite && open_out) set_flag(st, SPHV_F_OUT_OF_BOX);
+}
+
+// ---- exclusive scan of int32 (three passes)
+
+__device__ int block_scan_excl(int v, int* lds, int& total)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int add = t >= off ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    total = lds[kScanThreads - 1];
+    int excl = lds[t] - v;
+    __syncthreads();
+    return excl;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, int64_t m, int32_t* part)
+{
+    __shared__ int lds[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += in[base + k];
+    int total;
+    block_scan_excl(s, lds, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the block totals; part[nb] = grand total
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* part, int64_t nb)
+{
+    __shared__ int lds[kScanThreads];
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        int64_t b = b0 + threadIdx.x;
+        int v = b < nb ? part[b] : 0;
+        int total;
+        int ex = block_scan_excl(v, lds, total);
+        if (b < nb) part[b] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int64_t m, const int32_t* part,
+                                                             int32_t* out, int32_t* out2)
+{
+    __shared__ int lds[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < m ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_scan_excl(s, lds, total) + part[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) {
+            out[base + k] = ex;
+            if (out2) out2[base + k] = ex;
+        }
+        ex += v[k];
+    }
+    int64_t nb = (m + kScanTile - 1) / kScanTile;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = part[nb];
+}
+
+hipError_t scan_excl(const int32_t* in, int64_t m, int32_t* part, int32_t* out, int32_t* out2, hipStream_t s)
+{
+    int64_t nb = (m + kScanTile - 1) / kScanTile;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, m, part);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, m, part, out, out2);
+    return hipGetLastError();
+}
+
+__global__ void k_place(const int32_t* key, int64_t n, int32_t* cursor, int32_t* perm_tmp)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int pos = atomicAdd(&cursor[key[i]], 1);
+    perm_tmp[pos] = (int32_t)i;
+}
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
+
+// One wave per cell (grid-stride): order the cell's record indices ascending,
+// which, since the indices are distinct, is the stable order of the sort.
+__global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_start, const int32_t* perm_tmp,
+                                                          int32_t* perm, int32_t* key_sorted,
+                                                          const uint32_t* hmax_bits, int32_t* reach_d,
+                                                          int32_t* item_cnt, int32_t* meta, Geom g, int64_t nc)
+{
+    __shared__ int lds[kSortWaves][kSortLds];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    int* buf = lds[w];
+    int64_t wave_id = (int64_t)blockIdx.x * kSortWaves + w;
+    int64_t nwaves = (int64_t)gridDim.x * kSortWaves;
+    int rmax = 0;
+    for (int64_t c = wave_id; c < nc; c += nwaves) {
+        int b = cell_start[c], e = cell_start[c + 1];
+        int cnt = e - b;
+        if (cnt <= kWave) {
+            int v = lane < cnt ? perm_tmp[b + lane] : 0x7fffffff;
+            int rank = 0;
+            for (int k = 0; k < cnt; ++k) {
+                int u = __shfl(v, k, kWave);
+                rank += u < v;
+            }
+            if (lane < cnt) {
+                perm[b + rank] = v;
+                key_sorted[b + lane] = (int32_t)c;
+            }
+        } else if (cnt <= kSortLds) {
+            for (int k = lane; k < cnt; k += kWave) buf[k] = perm_tmp[b + k];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+            for (int k = lane; k < cnt; k += kWave) {
+                int v = buf[k];
+                int rank = 0;
+                for (int t = 0; t < cnt; ++t) rank += buf[t] < v;
+                perm[b + rank] = v;
+                key_sorted[b + k] = (int32_t)c;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            for (int k = lane; k < cnt; k += kWave) {
+                int v = perm_tmp[b + k];
+                int rank = 0;
+                for (int t = 0; t < cnt; ++t) rank += perm_tmp[b + t] < v;
+                perm[b + rank] = v;
+                key_sorted[b + k] = (int32_t)c;
+            }
+        }
+        if (lane == 0) {
+            int R = 0;
+            if (cnt > 0) {
+                float H = __uint_as_float(hmax_bits[c]);
+                R = (int)ceil((double)H / g.cmin);
+                if (R < 1) R = 1;
+            }
+            reach_d[c] = R;
+            item_cnt[c] = (cnt + kWave - 1) / kWave;
+            rmax = R > rmax ? R : rmax;
+        }
+    }
+    if (lane == 0 && rmax > 0) atomicMax(&meta[META_RGLOBAL], rmax);
+}
+
+__global__ void k_items(const int32_t* cell_start, const int32_t* item_start, int64_t nc, int64_t max_items,
+                        int4* items, int32_t* meta, DevState* st)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) {
+        int total = item_start[nc];
+        if (total > max_items) {
+            set_flag(st, SPHV_F_QUEUE_OVERFLOW);
+            total = (int)max_items;
+        }
+        meta[META_NITEMS] = total;
+    }
+    if (c >= nc) return;
+    int b = cell_start[c], e = cell_start[c + 1];
+    int o = item_start[c];
+    for (int f = b; f < e; f += kWave) {
+        if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 0);
+        ++o;
+    }
+}
+
+// box max of reach along one axis over +-R_global cells (wrapped or clipped)
+__global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, const int32_t* meta, int64_t nc,
+                             DevState* st)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int R = meta[META_RGLOBAL];
+    int n = g.n[axis];
+    if (g.periodic[axis] && 2 * R + 1 > n) {
+        if (c == 0) set_flag(st, SPHV_F_GRID_TOO_SMALL);
+        R = (n - 1) / 2;
+    }
+    int k[3];
+    cell_coords((int)c, g, k[0], k[1], k[2]);
+    int m = 0;
+    for (int d = -R; d <= R; ++d) {
+        int kk = k[axis] + d;
+        if (g.periodic[axis]) {
+            kk = ((kk % n) + n) % n;
+        } else if (kk < 0 || kk >= n) {
+            continue;
+        }
+        int q[3] = {k[0], k[1], k[2]};
+        q[axis] = kk;
+        int v = in[cell_key(q[0], q[1], q[2], g)];
+        m = v > m ? v : m;
+    }
+    out[c] = m;
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    unsigned b = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(b), dim3(256), 0, s, (uint32_t*)p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_init(DevState* st, int full, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access& rec, const Geom& g, DevState* st,
+                              hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_fill_u32(c.counts, 0u, c.nc, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(c.hmax_bits, 0u, c.nc, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(c.meta, 0u, META_SIZE, s)) != hipSuccess) return e;
+    if (c.n > 0) {
+        hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride, g,
+                           c.n, c.key, c.counts, c.hmax_bits, st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = scan_excl(c.counts, c.nc, c.scan_part, c.cell_start, c.cursor, s)) != hipSuccess) return e;
+    if (c.n > 0) {
+        hipLaunchKernelGGL(k_place, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.key, c.n, c.cursor, c.perm_tmp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    unsigned sb = (unsigned)std::min<int64_t>((c.nc + kSortWaves - 1) / kSortWaves, 8192);
+    hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
+                       c.key_sorted, c.hmax_bits, c.reach_d, c.tmp_a, c.meta, g, c.nc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.nc,
+                       c.max_items, c.items, c.meta, st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.reach_d, c.tmp_b, g, 0, c.meta,
+                       c.nc, st);
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_b, c.tmp_a, g, 1, c.meta,
+                       c.nc, st);
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.reach_f, g, 2, c.meta,
+                       c.nc, st);
+    return hipGetLastError();
+}
+
+}  // namespace sphv

@@ -1,0 +1,137 @@
+// View conversions and the linear kick/drift loop.
+//
+// gather  (prologue, N o C of the paper's eq. "view"): view[p].f = record[index[p]].f
+//         for every member f in A_in; f64 members are bit copies (NaN payloads
+//         kept), or, in an FP32 view, rounded to float (positions relative to
+//         the lower corner of their cell).
+// scatter (epilogue, C^T o W): record[index[p]].f = view[p].f for f in A_out only.
+// kick_drift: per record, every product and sum rounded on its own.
+#include "k_common.h"
+
+namespace sphv {
+
+namespace {
+
+struct FieldPack {
+    FieldRef src[kMaxFields];
+    FieldRef dst[kMaxFields];
+};
+
+constexpr int kConvThreads = 256;
+
+// one thread per view element p; the record's members come from one record span
+__global__ __launch_bounds__(kConvThreads) void k_gather(FieldPack fp, int nf, Access sa, Access da,
+                                                         const int32_t* cell_key, Geom g, int64_t n)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    Loc<true> ls = locate<true>(sa, p);
+    Loc<false> ld = locate<false>(da, p);
+    int key = cell_key ? cell_key[sa.index ? sa.index[p] : p] : 0;
+    for (int k = 0; k < nf; ++k) {
+        const FieldRef& s = fp.src[k];
+        const FieldRef& d = fp.dst[k];
+        if (s.size == 8 && d.size == 8) {
+            *(uint64_t*)ld.at(d) = *(const uint64_t*)ls.at(s);
+        } else if (s.size == 4 && d.size == 4) {
+            *(uint32_t*)ld.at(d) = *(const uint32_t*)ls.at(s);
+        } else {
+            // f64 member narrowed to float (FP32 view); d carries rel_axis
+            FieldRef q = s;
+            q.rel_axis = d.rel_axis;
+            *(float*)ld.at(d) = ld_as_f32(q, ls, g, key);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kConvThreads) void k_scatter(FieldPack fp, int nf, Access sa, Access da, int64_t n)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    Loc<false> ls = locate<false>(sa, p);
+    Loc<true> ld = locate<true>(da, p);
+    for (int k = 0; k < nf; ++k) {
+        const FieldRef& s = fp.src[k];
+        const FieldRef& d = fp.dst[k];
+        if (d.size == 8) *(uint64_t*)ld.at(d) = *(const uint64_t*)ls.at(s);
+        else *(uint32_t*)ld.at(d) = *(const uint32_t*)ls.at(s);
+    }
+}
+
+struct KickFields {
+    FieldRef f[15];   // x y z vx vy vz vhx vhy vhz ax ay az u uh u_dt
+};
+
+__global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint64_t stride, Geom g,
+                                                             const DevState* st, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = st->dt;
+    const double dt_prev = st->dt_prev;
+    const bool first = st->nstep <= 1;
+    const double half = __dmul_rn(0.5, dt);
+    const double half_prev = __dmul_rn(0.5, dt_prev);
+    uint64_t rb = (uint64_t)i * stride;
+    auto P = [&](int k) -> double* { return (double*)(kf.f[k].base + kf.f[k].off + rb); };
+    for (int d = 0; d < 3; ++d) {
+        double a = *P(9 + d);
+        double v = *P(3 + d);
+        if (!first) v = __dadd_rn(*P(6 + d), __dmul_rn(a, half_prev));     // close the previous step
+        double vh = __dadd_rn(v, __dmul_rn(a, half));                       // open this step
+        double x = __dadd_rn(*P(d), __dmul_rn(vh, dt));                     // drift
+        if (g.periodic[d]) {
+            double hi = __dadd_rn(g.lo[d], g.len[d]);
+            if (x >= hi) x = __dsub_rn(x, g.len[d]);
+            else if (x < g.lo[d]) x = __dadd_rn(x, g.len[d]);
+        }
+        *P(d) = x;
+        *P(6 + d) = vh;
+        *P(3 + d) = __dadd_rn(vh, __dmul_rn(a, half));                      // predict
+    }
+    double du = *P(14);
+    double u = *P(12);
+    if (!first) u = __dadd_rn(*P(13), __dmul_rn(du, half_prev));
+    double uh = __dadd_rn(u, __dmul_rn(du, half));
+    *P(13) = uh;
+    *P(12) = __dadd_rn(uh, __dmul_rn(du, half));
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kConvThreads - 1) / kConvThreads); }
+
+}  // namespace
+
+hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& sa, const Access& da,
+                         const int32_t* cell_key, const Geom& g, int64_t n, hipStream_t s)
+{
+    FieldPack fp;
+    for (int k = 0; k < nf; ++k) {
+        fp.src[k] = src[k];
+        fp.dst[k] = dst[k];
+    }
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, cell_key, g, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, const Access& sa, const Access& da,
+                          int64_t n, hipStream_t s)
+{
+    FieldPack fp;
+    for (int k = 0; k < nf; ++k) {
+        fp.src[k] = src[k];
+        fp.dst[k] = dst[k];
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g, const DevState* st, int64_t n,
+                             hipStream_t s)
+{
+    KickFields kf;
+    for (int k = 0; k < 15; ++k) kf.f[k] = f[k];
+    hipLaunchKernelGGL(k_kick_drift, dim3(nblk(n)), dim3(kConvThreads), 0, s, kf, rec.stride, g, st, n);
+    return hipGetLastError();
+}
+
+}  // namespace sphv

@@ -1,0 +1,470 @@
+"""Python binding of libsphview.so (ctypes).  Argument marshalling only: every
+step of the SPH path runs in the library's HIP kernels.  torch provides device
+memory (workspaces are uint8 tensors) and streams.
+
+Function names are the C entry points without the ``sphv_`` prefix.  A missing
+library raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphview.so")
+
+# ------------------------------------------------------------ constants
+
+OK, E_INVALID_ARG, E_DESCRIPTOR, E_WORKSPACE, E_ALIAS, E_STATE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+F_NONFINITE_INPUT, F_H_NOT_CONVERGED, F_H_CAP_HIT, F_QUEUE_OVERFLOW = 1, 2, 4, 8
+F_NONFINITE_OUTPUT, F_GRID_TOO_SMALL, F_OUT_OF_BOX = 16, 32, 64
+F64, F32, I64, I32 = 1, 2, 3, 4
+IN, OUT, INOUT = 1, 2, 3
+LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+
+ROLES = ["user", "x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "ax", "ay", "az", "m", "h", "rho",
+         "omega", "u", "uh", "u_dt", "alpha", "v_sig", "wcount"]
+ROLE = {name: i for i, name in enumerate(ROLES)}
+
+EXPORTS = [
+    "sphv_status_string", "sphv_version", "sphv_params_init", "sphv_state_bytes", "sphv_state_init",
+    "sphv_begin_step", "sphv_read_state", "sphv_write_state", "sphv_cells_workspace_bytes", "sphv_cells_create",
+    "sphv_cells_build", "sphv_cells_get_info", "sphv_cells_destroy", "sphv_view_workspace_bytes",
+    "sphv_view_create", "sphv_aos_to_soa", "sphv_soa_to_aos", "sphv_view_field", "sphv_view_destroy",
+    "sphv_sph_density", "sphv_sph_force", "sphv_step_reduce", "sphv_kick_drift", "sphv_graph_begin", "sphv_graph_end",
+    "sphv_graph_launch", "sphv_graph_destroy",
+]
+
+
+class Field(C.Structure):
+    _fields_ = [("offset", C.c_uint64), ("role", C.c_uint32), ("dtype", C.c_uint16), ("access", C.c_uint16)]
+
+
+class Descriptor(C.Structure):
+    _fields_ = [("stride", C.c_uint64), ("n_fields", C.c_uint32), ("reserved", C.c_uint32),
+                ("fields", C.POINTER(Field))]
+
+
+class Params(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3), ("cell", C.c_double * 3),
+                ("inv_cell", C.c_double * 3), ("grid", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+                ("gamma", C.c_double), ("eta", C.c_double), ("cfl", C.c_double), ("h_tol", C.c_double),
+                ("headroom", C.c_double), ("max_iter", C.c_int32), ("reserved", C.c_int32)]
+
+
+class State(C.Structure):
+    _fields_ = [("flags", C.c_uint32), ("max_iters", C.c_int32), ("nstep", C.c_int64), ("dt", C.c_double),
+                ("dt_prev", C.c_double), ("t", C.c_double), ("sums", C.c_double * 8),
+                ("pairs_density", C.c_int64), ("pairs_force", C.c_int64), ("pair_evals_density", C.c_int64),
+                ("pairs_total", C.c_int64), ("reserved", C.c_int64 * 3)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("aosoa_width", C.c_uint32), ("tpi", C.c_uint32), ("masked", C.c_uint32)]
+
+
+class CellsInfo(C.Structure):
+    _fields_ = [("perm", C.c_void_p), ("cell_start", C.c_void_p), ("key", C.c_void_p), ("reach", C.c_void_p),
+                ("n", C.c_int64), ("n_cells", C.c_int64), ("max_items", C.c_int64)]
+
+
+class SphvError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_LIB = None
+VP = C.c_void_p
+
+
+def lib():
+    """Load libsphview.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (or python -m "
+                          f"paper_2502_16517_amd._build) first; there is no non-HIP fallback")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "sphv_status_string": (C.c_char_p, [C.c_int32]),
+        "sphv_version": (C.c_int32, []),
+        "sphv_params_init": (C.c_int32, [C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "sphv_state_bytes": (C.c_size_t, []),
+        "sphv_state_init": (C.c_int32, [VP, VP]),
+        "sphv_begin_step": (C.c_int32, [VP, VP]),
+        "sphv_read_state": (C.c_int32, [VP, C.POINTER(State), VP]),
+        "sphv_write_state": (C.c_int32, [VP, C.POINTER(State), VP]),
+        "sphv_cells_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Params)]),
+        "sphv_cells_create": (C.c_int32, [C.POINTER(VP), C.c_int64, C.POINTER(Params), VP, C.c_size_t]),
+        "sphv_cells_build": (C.c_int32, [VP, VP, C.POINTER(Descriptor), VP, VP]),
+        "sphv_cells_get_info": (C.c_int32, [VP, C.POINTER(CellsInfo)]),
+        "sphv_cells_destroy": (None, [VP]),
+        "sphv_view_workspace_bytes": (C.c_size_t, [C.POINTER(Descriptor), C.c_int64, C.POINTER(Layout),
+                                                   C.c_int32]),
+        "sphv_view_create": (C.c_int32, [C.POINTER(VP), C.POINTER(Descriptor), C.c_int64, C.POINTER(Layout),
+                                         C.c_int32, VP, VP, VP, C.c_size_t]),
+        "sphv_aos_to_soa": (C.c_int32, [VP, VP, VP]),
+        "sphv_soa_to_aos": (C.c_int32, [VP, VP]),
+        "sphv_view_field": (C.c_int32, [VP, C.c_uint32, C.POINTER(VP), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "sphv_view_destroy": (None, [VP]),
+        "sphv_sph_density": (C.c_int32, [VP, VP, C.POINTER(Params), VP, VP]),
+        "sphv_sph_force": (C.c_int32, [VP, VP, C.POINTER(Params), VP, VP]),
+        "sphv_step_reduce": (C.c_int32, [VP, C.POINTER(Params), VP, VP]),
+        "sphv_kick_drift": (C.c_int32, [VP, C.POINTER(Descriptor), C.c_int64, C.POINTER(Params), VP, VP]),
+        "sphv_graph_begin": (C.c_int32, [VP]),
+        "sphv_graph_end": (C.c_int32, [VP, C.POINTER(VP)]),
+        "sphv_graph_launch": (C.c_int32, [VP, VP]),
+        "sphv_graph_destroy": (None, [VP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().sphv_status_string(int(s)).decode()
+
+
+def _chk(s: int, what: str) -> None:
+    if s != OK:
+        raise SphvError(s, what)
+
+
+def _ptr(x) -> int | None:
+    """Device (or host) address of a torch tensor, or an int address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------ descriptors
+
+def descriptor(fields, stride: int = inputs.STRIDE):
+    """fields: iterable of (role name or None, offset bytes, dtype, access)."""
+    fl = list(fields)
+    arr = (Field * max(1, len(fl)))()
+    for k, (role, off, dt, acc) in enumerate(fl):
+        arr[k].offset = off
+        arr[k].role = ROLE[role] if role else 0
+        arr[k].dtype = dt
+        arr[k].access = acc
+    d = Descriptor(stride, len(fl), 0, C.cast(arr, C.POINTER(Field)))
+    d._keep = arr
+    return d
+
+
+def _rec_fields(spec):
+    return [(name, inputs.SLOT[name] * 8, F64, acc) for name, acc in spec]
+
+
+DENSITY_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("m", IN), ("h", INOUT), ("rho", OUT), ("omega", OUT),
+                  ("wcount", OUT)]
+FORCE_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("vx", IN), ("vy", IN), ("vz", IN), ("m", IN), ("h", IN),
+                ("rho", IN), ("omega", IN), ("u", IN), ("alpha", IN), ("ax", OUT), ("ay", OUT), ("az", OUT),
+                ("u_dt", OUT), ("v_sig", OUT)]
+KICK_FIELDS = [("x", INOUT), ("y", INOUT), ("z", INOUT), ("vx", INOUT), ("vy", INOUT), ("vz", INOUT),
+               ("vhx", INOUT), ("vhy", INOUT), ("vhz", INOUT), ("ax", IN), ("ay", IN), ("az", IN),
+               ("u", INOUT), ("uh", INOUT), ("u_dt", IN)]
+CELLS_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("h", IN)]
+
+
+def density_descriptor():
+    return descriptor(_rec_fields(DENSITY_FIELDS))
+
+
+def force_descriptor():
+    return descriptor(_rec_fields(FORCE_FIELDS))
+
+
+def kick_descriptor():
+    return descriptor(_rec_fields(KICK_FIELDS))
+
+
+def cells_descriptor():
+    return descriptor(_rec_fields(CELLS_FIELDS))
+
+
+def soa_descriptor(spec, n: int, base_slots=None):
+    """Descriptor of a struct-of-arrays store: member k is an array of n doubles
+    at byte offset slot_k * n * 8 (slot_k from the record layout)."""
+    fl = []
+    for name, acc in spec:
+        slot = inputs.SLOT[name] if base_slots is None else base_slots[name]
+        fl.append((name, slot * n * 8, F64, acc))
+    return descriptor(fl, stride=8)
+
+
+# ------------------------------------------------------------ params / layout
+
+def params_init(lo, length, grid, periodic, **kw) -> Params:
+    p = Params()
+    lo_a = (C.c_double * 3)(*lo)
+    le_a = (C.c_double * 3)(*length)
+    g_a = (C.c_int32 * 3)(*grid)
+    pe_a = (C.c_int32 * 3)(*periodic)
+    _chk(lib().sphv_params_init(C.byref(p), lo_a, le_a, g_a, pe_a), "params_init")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def layout(kind=LAYOUT_SOA, aosoa_width=0, tpi=0, masked=0) -> Layout:
+    return Layout(kind, aosoa_width, tpi, masked)
+
+
+# ------------------------------------------------------------ state
+
+def state_bytes() -> int:
+    return int(lib().sphv_state_bytes())
+
+
+def state_init(state, stream=None):
+    _chk(lib().sphv_state_init(_ptr(state), _stream(stream)), "state_init")
+
+
+def begin_step(state, stream=None):
+    _chk(lib().sphv_begin_step(_ptr(state), _stream(stream)), "begin_step")
+
+
+def read_state(state, stream=None) -> State:
+    s = State()
+    _chk(lib().sphv_read_state(_ptr(state), C.byref(s), _stream(stream)), "read_state")
+    return s
+
+
+def write_state(state, s: State, stream=None):
+    _chk(lib().sphv_write_state(_ptr(state), C.byref(s), _stream(stream)), "write_state")
+
+
+# ------------------------------------------------------------ cells
+
+def cells_workspace_bytes(n: int, p: Params) -> int:
+    return int(lib().sphv_cells_workspace_bytes(n, C.byref(p)))
+
+
+def cells_create(n: int, p: Params, ws, ws_bytes: int | None = None):
+    h = VP()
+    nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
+    _chk(lib().sphv_cells_create(C.byref(h), n, C.byref(p), _ptr(ws), nb), "cells_create")
+    return h
+
+
+def cells_build(cells, aos, d: Descriptor, state, stream=None):
+    _chk(lib().sphv_cells_build(cells, _ptr(aos), C.byref(d), _ptr(state), _stream(stream)), "cells_build")
+
+
+def cells_get_info(cells) -> CellsInfo:
+    info = CellsInfo()
+    _chk(lib().sphv_cells_get_info(cells, C.byref(info)), "cells_get_info")
+    return info
+
+
+def cells_destroy(cells):
+    lib().sphv_cells_destroy(cells)
+
+
+# ------------------------------------------------------------ views
+
+def view_workspace_bytes(d: Descriptor, n: int, l: Layout, precision: int) -> int:
+    return int(lib().sphv_view_workspace_bytes(C.byref(d), n, C.byref(l), precision))
+
+
+def view_create(d: Descriptor, n: int, l: Layout, precision: int, aos, index, ws, ws_bytes: int | None = None):
+    h = VP()
+    nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
+    _chk(lib().sphv_view_create(C.byref(h), C.byref(d), n, C.byref(l), precision, _ptr(aos), _ptr(index),
+                                _ptr(ws), nb), "view_create")
+    return h
+
+
+def aos_to_soa(view, cells=None, stream=None):
+    _chk(lib().sphv_aos_to_soa(view, cells, _stream(stream)), "aos_to_soa")
+
+
+def soa_to_aos(view, stream=None):
+    _chk(lib().sphv_soa_to_aos(view, _stream(stream)), "soa_to_aos")
+
+
+def view_field(view, k: int):
+    ptr, dt, bl, bb = VP(), C.c_int32(), C.c_uint64(), C.c_uint64()
+    _chk(lib().sphv_view_field(view, k, C.byref(ptr), C.byref(dt), C.byref(bl), C.byref(bb)), "view_field")
+    return ptr.value, dt.value, bl.value, bb.value
+
+
+def view_destroy(view):
+    lib().sphv_view_destroy(view)
+
+
+def sph_density(view, cells, p: Params, state, stream=None):
+    _chk(lib().sphv_sph_density(view, cells, C.byref(p), _ptr(state), _stream(stream)), "sph_density")
+
+
+def sph_force(view, cells, p: Params, state, stream=None):
+    _chk(lib().sphv_sph_force(view, cells, C.byref(p), _ptr(state), _stream(stream)), "sph_force")
+
+
+def step_reduce(view, p: Params, state, stream=None):
+    _chk(lib().sphv_step_reduce(view, C.byref(p), _ptr(state), _stream(stream)), "step_reduce")
+
+
+def kick_drift(aos, d: Descriptor, n: int, p: Params, state, stream=None):
+    _chk(lib().sphv_kick_drift(_ptr(aos), C.byref(d), n, C.byref(p), _ptr(state), _stream(stream)),
+         "kick_drift")
+
+
+# ------------------------------------------------------------ graphs
+
+def graph_begin(stream):
+    _chk(lib().sphv_graph_begin(_stream(stream)), "graph_begin")
+
+
+def graph_end(stream):
+    g = VP()
+    _chk(lib().sphv_graph_end(_stream(stream), C.byref(g)), "graph_end")
+    return g
+
+
+def graph_launch(g, stream):
+    _chk(lib().sphv_graph_launch(g, _stream(stream)), "graph_launch")
+
+
+def graph_destroy(g):
+    lib().sphv_graph_destroy(g)
+
+
+# ------------------------------------------------------------ step driver
+
+class Stepper:
+    """Owns the device buffers of one particle set and runs whole SPH steps
+    through the C-ABI: cells_build, the density view (gather, density, scatter),
+    the force view (gather, force + dt + sums, scatter) and kick_drift.
+
+    layout_density / layout_force: Layout of each view (SPHV_LAYOUT_DIRECT runs
+    the loops on the records themselves).  aos may be an (n*256,) uint8 device
+    tensor holding 256-byte records, or None to upload ``rec``.
+    """
+
+    def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
+                 layout_density: Layout | None = None, layout_force: Layout | None = None,
+                 device="cuda", aos=None, stream=None):
+        import torch
+        self.torch = torch
+        self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
+        self.p = params
+        self.precision = precision
+        self.ld = layout_density or layout()
+        self.lf = layout_force or layout()
+        self.stream = stream
+        self.device = device
+        if aos is None:
+            aos = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(rec))).to(device)
+        self.aos = aos
+        u8 = dict(dtype=torch.uint8, device=device)
+        self.state = torch.zeros(state_bytes(), **u8)
+        self.cells_ws = torch.empty(max(256, cells_workspace_bytes(self.n, params)), **u8)
+        self.cells = cells_create(self.n, params, self.cells_ws)
+        self.d_cells = cells_descriptor()
+        self.d_dens = density_descriptor()
+        self.d_force = force_descriptor()
+        self.d_kick = kick_descriptor()
+        self.ws_dens = torch.empty(max(256, view_workspace_bytes(self.d_dens, self.n, self.ld, precision)), **u8)
+        self.ws_force = torch.empty(max(256, view_workspace_bytes(self.d_force, self.n, self.lf, precision)), **u8)
+        info = cells_get_info(self.cells)
+        self.perm_ptr = info.perm
+        self.v_dens = view_create(self.d_dens, self.n, self.ld, precision, self.aos, self.perm_ptr, self.ws_dens)
+        self.v_force = view_create(self.d_force, self.n, self.lf, precision, self.aos, self.perm_ptr,
+                                   self.ws_force)
+        state_init(self.state, self.stream)
+
+    # the pieces of a step, in order
+    def build(self):
+        begin_step(self.state, self.stream)
+        cells_build(self.cells, self.aos, self.d_cells, self.state, self.stream)
+
+    def density(self):
+        aos_to_soa(self.v_dens, self.cells, self.stream)
+        sph_density(self.v_dens, self.cells, self.p, self.state, self.stream)
+        soa_to_aos(self.v_dens, self.stream)
+
+    def force(self):
+        aos_to_soa(self.v_force, self.cells, self.stream)
+        sph_force(self.v_force, self.cells, self.p, self.state, self.stream)
+        step_reduce(self.v_force, self.p, self.state, self.stream)
+        soa_to_aos(self.v_force, self.stream)
+
+    def kick(self):
+        kick_drift(self.aos, self.d_kick, self.n, self.p, self.state, self.stream)
+
+    def step(self):
+        self.build()
+        self.density()
+        self.force()
+        self.kick()
+
+    def read_state(self) -> State:
+        return read_state(self.state, self.stream)
+
+    def records(self) -> np.ndarray:
+        self.torch.cuda.synchronize()
+        return self.aos.cpu().numpy().view(np.float64).reshape(self.n, inputs.NSLOT).copy()
+
+    def cells_arrays(self):
+        """perm, cell_start, key (host copies) of the last cells_build."""
+        import torch
+        info = cells_get_info(self.cells)
+        nc = info.n_cells
+        ws = self.cells_ws
+        base = ws.data_ptr()
+
+        def view_i32(ptr, count):
+            off = ptr - base
+            return ws[off:off + 4 * count].view(torch.int32).cpu().numpy().copy()
+
+        torch.cuda.synchronize()
+        return (view_i32(info.perm, self.n), view_i32(info.cell_start, nc + 1), view_i32(info.key, self.n),
+                view_i32(info.reach, 2 * nc))
+
+    def close(self):
+        for v in (getattr(self, "v_dens", None), getattr(self, "v_force", None)):
+            if v:
+                view_destroy(v)
+        if getattr(self, "cells", None):
+            cells_destroy(self.cells)
+        self.v_dens = self.v_force = self.cells = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params_for(w, **kw) -> Params:
+    """Params of a generated workload (inputs.Workload)."""
+    p = params_init(w.lo, w.length, w.grid, w.periodic)
+    p.eta = w.eta
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p

@@ -1,0 +1,99 @@
+"""Shared helpers of the GPU parity tests: run pieces of the HIP path through
+the C-ABI and the oracle on the same seeded inputs, and the error metric.
+
+Error metric for accumulated outputs: e_i = |x_gpu - x_ref| / S_i with S_i the
+sum of the magnitudes of the pair terms (returned by the oracle), so that sums
+that nearly cancel are judged against the size of what was summed; h and omega
+are judged by plain relative error."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2502_16517_amd import inputs
+from paper_2502_16517_amd import sphview as sv
+
+S = inputs.SLOT
+
+
+def cols(rec):
+    return {k: rec[:, S[k]].copy() for k in S if k not in inputs.INT_SLOTS}
+
+
+def box(orc, w):
+    return orc.box_of(w.lo, w.length, w.periodic)
+
+
+def run_density(w, precision=sv.PREC_FP64, lay=None, tol=None, rec=None, max_iter=16, **pkw):
+    """cells_build + density view (gather, density, scatter) on the GPU."""
+    r = w.rec if rec is None else rec
+    p = sv.params_for(w, **pkw)
+    if tol is not None:
+        p.h_tol = tol
+    p.max_iter = max_iter
+    st = sv.Stepper(r, p, precision, layout_density=lay, layout_force=lay)
+    st.build()
+    st.density()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    return out, state
+
+
+def run_density_force(w, precision=sv.PREC_FP64, lay=None, tol=None, rec=None, **pkw):
+    r = w.rec if rec is None else rec
+    p = sv.params_for(w, **pkw)
+    if tol is not None:
+        p.h_tol = tol
+    st = sv.Stepper(r, p, precision, layout_density=lay, layout_force=lay)
+    st.build()
+    st.density()
+    after_density = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    return after_density, out, state
+
+
+def oracle_density(orc, w, rec=None, targets=None, tol=1e-13):
+    r = w.rec if rec is None else rec
+    c = cols(r)
+    return orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box(orc, w), w.eta, tol=tol, max_iter=16,
+                       targets=targets)
+
+
+def oracle_force(orc, w, rec, targets=None):
+    c = cols(rec)
+    return orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], c["h"], c["rho"], c["omega"],
+                     c["u"], c["alpha"], box(orc, w), inputs.GAMMA, targets=targets)
+
+
+def rel(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+def check_density(gpu_rec, ref, idx=None, tol=1e-12, counts=None):
+    g = gpu_rec if idx is None else gpu_rec[idx]
+    eh = rel(g[:, S["h"]], ref["h"])
+    erho = rel(g[:, S["rho"]], ref["rho"])
+    eom = rel(g[:, S["omega"]], ref["omega"])
+    ewc = rel(g[:, S["wcount"]], ref["wcount"])
+    worst = {"h": eh.max(), "rho": erho.max(), "omega": eom.max(), "wcount": ewc.max()}
+    assert all(v <= tol for v in worst.values()), worst
+    return worst
+
+
+def check_force(gpu_rec, ref, idx=None, tol=1e-12, vsig_tol=None):
+    g = gpu_rec if idx is None else gpu_rec[idx]
+    da = np.sqrt(sum((g[:, S[k]] - ref[k]) ** 2 for k in ("ax", "ay", "az")))
+    ea = da / ref["sa"]
+    eu = np.abs(g[:, S["u_dt"]] - ref["udot"]) / np.maximum(ref["su"], 1e-300)
+    ev = rel(g[:, S["v_sig"]], ref["vsig"])
+    worst = {"a": ea.max(), "u_dt": eu.max(), "v_sig": ev.max()}
+    vt = tol if vsig_tol is None else vsig_tol
+    assert worst["a"] <= tol and worst["u_dt"] <= tol and worst["v_sig"] <= vt, worst
+    return worst
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)

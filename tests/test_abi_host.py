@@ -1,0 +1,200 @@
+"""Host-side checks of libsphview.so that need no GPU: the library loads, exports
+every entry point that include/sphview.h declares, and its host logic (status
+strings, parameter set-up, descriptor validation, workspace planning, the
+open-view alias rule) behaves as documented.  No device work is enqueued."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2502_16517_amd import inputs
+from paper_2502_16517_amd import sphview as sv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return sv.lib()
+
+
+def declared_entry_points():
+    text = open(os.path.join(ROOT, "include", "sphview.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sphv_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_entry_points()
+    assert len(names) >= 26
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sv.EXPORTS)
+
+
+def test_version_and_status_strings(L):
+    assert L.sphv_version() >= 100
+    for s in range(-7, 1):
+        assert sv.status_string(s) not in ("", "unknown status")
+    assert sv.status_string(-99) == "unknown status"
+
+
+def test_state_block_size():
+    assert sv.state_bytes() == C.sizeof(sv.State)
+
+
+def test_params_init():
+    p = sv.params_init((0, 0, 0), (2.0, 1.0, 1.0), (48, 24, 24), (1, 1, 1))
+    assert p.cell[0] == 2.0 / 48 and p.inv_cell[1] == 24.0
+    assert p.gamma == 5.0 / 3.0 and p.max_iter == 16 and p.h_tol == 1e-13
+    with pytest.raises(sv.SphvError):
+        sv.params_init((0, 0, 0), (0.0, 1.0, 1.0), (4, 4, 4), (1, 1, 1))
+
+
+def _ws_bytes(fields, n=100, stride=256, l=None, prec=sv.PREC_FP64):
+    d = sv.descriptor(fields, stride)
+    return sv.view_workspace_bytes(d, n, l or sv.layout(), prec)
+
+
+def test_descriptor_validation():
+    ok = [("x", 0, sv.F64, sv.IN), ("h", 104, sv.F64, sv.INOUT)]
+    assert _ws_bytes(ok) > 0
+    # overlapping members
+    assert _ws_bytes([("x", 0, sv.F64, sv.IN), ("y", 4, sv.F32, sv.IN)]) == 0
+    # misaligned
+    assert _ws_bytes([("x", 4, sv.F64, sv.IN)]) == 0
+    # bad dtype / access / role
+    assert _ws_bytes([("x", 0, 9, sv.IN)]) == 0
+    assert _ws_bytes([("x", 0, sv.F64, 0)]) == 0
+    # duplicate role
+    assert _ws_bytes([("x", 0, sv.F64, sv.IN), ("x", 8, sv.F64, sv.IN)]) == 0
+    # struct of arrays: stride == member size, whole arrays disjoint
+    n = 100
+    assert _ws_bytes([("x", 0, sv.F64, sv.IN), ("y", 8 * n, sv.F64, sv.IN)], n=n, stride=8) > 0
+    assert _ws_bytes([("x", 0, sv.F64, sv.IN), ("y", 8 * n - 8, sv.F64, sv.IN)], n=n, stride=8) == 0
+
+
+def test_workspace_sizes():
+    d = sv.density_descriptor()
+    a = sv.view_workspace_bytes(d, 1000, sv.layout(), sv.PREC_FP64)
+    b = sv.view_workspace_bytes(d, 2000, sv.layout(), sv.PREC_FP64)
+    c = sv.view_workspace_bytes(d, 1000, sv.layout(), sv.PREC_FP32)
+    e = sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_DIRECT), sv.PREC_FP64)
+    f = sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 16), sv.PREC_FP64)
+    assert 0 < e < c < a < b
+    assert f >= 1000 * 8 * 8
+    # 8 members x 8 B per element at least
+    assert a >= 1000 * 64
+    # AoSoA width must be a power of two in [8, 1024]
+    assert sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 12), sv.PREC_FP64) == 0
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    assert sv.cells_workspace_bytes(4096, p) > 4096 * 16 + 216 * 4
+
+
+def test_view_create_errors():
+    d = sv.density_descriptor()
+    l = sv.layout()
+    need = sv.view_workspace_bytes(d, 10, l, sv.PREC_FP64)
+    fake = 1 << 40                                     # aligned, never dereferenced by the host
+    with pytest.raises(sv.SphvError) as e:
+        sv.view_create(d, 10, l, sv.PREC_FP64, fake, None, fake, need - 1)
+    assert e.value.status == sv.E_WORKSPACE
+    with pytest.raises(sv.SphvError) as e:
+        sv.view_create(d, 10, l, sv.PREC_FP64, fake, None, fake + 8, need)
+    assert e.value.status == sv.E_WORKSPACE
+    with pytest.raises(sv.SphvError) as e:
+        sv.view_create(d, 10, sv.layout(tpi=65), sv.PREC_FP64, fake, None, fake, need)
+    assert e.value.status == sv.E_INVALID_ARG
+    v = sv.view_create(d, 10, l, sv.PREC_FP64, fake, None, fake, need)
+    ptr, dt, bl, bb = sv.view_field(v, 0)
+    assert ptr == fake and dt == sv.F64 and bl == 10
+    ptr1, _, _, _ = sv.view_field(v, 1)
+    assert ptr1 - fake >= 80 and (ptr1 - fake) % 256 == 0
+    sv.view_destroy(v)
+
+
+def test_fp32_view_member_types():
+    d = sv.force_descriptor()
+    l = sv.layout()
+    need = sv.view_workspace_bytes(d, 10, l, sv.PREC_FP32)
+    fake = 1 << 40
+    v = sv.view_create(d, 10, l, sv.PREC_FP32, fake, None, fake, need)
+    types = [sv.view_field(v, k)[1] for k in range(len(sv.FORCE_FIELDS))]
+    # members only read become float, written members stay double
+    for (name, acc), t in zip(sv.FORCE_FIELDS, types):
+        assert t == (sv.F32 if acc == sv.IN else sv.F64), name
+    sv.view_destroy(v)
+
+
+def test_alias_rule_between_open_views():
+    """A second view may not open on the same records while an open view writes
+    what it touches (paper Sec. 3.3).  n = 0 views enqueue no device work."""
+    fake = 1 << 40
+    dd, df = sv.density_descriptor(), sv.force_descriptor()
+    l = sv.layout()
+    vd = sv.view_create(dd, 0, l, sv.PREC_FP64, fake, None, fake, 1 << 20)
+    vf = sv.view_create(df, 0, l, sv.PREC_FP64, fake, None, fake + (1 << 20), 1 << 20)
+    sv.aos_to_soa(vd)
+    with pytest.raises(sv.SphvError) as e:
+        sv.aos_to_soa(vf)                 # force reads h, rho, omega that density writes
+    assert e.value.status == sv.E_ALIAS
+    # a view on other records is fine
+    vo = sv.view_create(df, 0, l, sv.PREC_FP64, fake + (1 << 30), None, fake + (2 << 20), 1 << 20)
+    sv.aos_to_soa(vo)
+    sv.soa_to_aos(vo)
+    sv.soa_to_aos(vd)
+    sv.aos_to_soa(vf)                     # density view closed: no conflict
+    with pytest.raises(sv.SphvError) as e:
+        sv.aos_to_soa(vf)                 # already open
+    assert e.value.status == sv.E_STATE
+    sv.soa_to_aos(vf)
+    with pytest.raises(sv.SphvError) as e:
+        sv.soa_to_aos(vf)                 # not open
+    assert e.value.status == sv.E_STATE
+    for v in (vd, vf, vo):
+        sv.view_destroy(v)
+
+
+def test_disjoint_views_do_not_conflict():
+    fake = 1 << 40
+    l = sv.layout()
+    a = sv.descriptor([("x", 0, sv.F64, sv.IN), ("ax", 72, sv.F64, sv.OUT)])
+    b = sv.descriptor([("y", 8, sv.F64, sv.IN), ("ay", 80, sv.F64, sv.OUT)])
+    va = sv.view_create(a, 0, l, sv.PREC_FP64, fake, None, fake, 1 << 16)
+    vb = sv.view_create(b, 0, l, sv.PREC_FP64, fake, None, fake + (1 << 16), 1 << 16)
+    sv.aos_to_soa(va)
+    sv.aos_to_soa(vb)
+    sv.soa_to_aos(va)
+    sv.soa_to_aos(vb)
+    sv.view_destroy(va)
+    sv.view_destroy(vb)
+
+
+def test_loop_calls_need_an_open_view_and_built_cells():
+    fake = 1 << 40
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    cws = sv.cells_workspace_bytes(10, p)
+    cells = sv.cells_create(10, p, fake, cws)
+    d = sv.density_descriptor()
+    v = sv.view_create(d, 10, sv.layout(sv.LAYOUT_DIRECT), sv.PREC_FP64, fake, None, fake, 1 << 16)
+    with pytest.raises(sv.SphvError) as e:
+        sv.sph_density(v, cells, p, fake)
+    assert e.value.status == sv.E_STATE            # view not open
+    sv.aos_to_soa(v)                               # direct layout: opens without device work
+    with pytest.raises(sv.SphvError) as e:
+        sv.sph_density(v, cells, p, fake)
+    assert e.value.status == sv.E_STATE            # cells never built
+    # a descriptor without the density roles
+    d2 = sv.descriptor([("x", 0, sv.F64, sv.IN)])
+    v2 = sv.view_create(d2, 10, sv.layout(sv.LAYOUT_DIRECT), sv.PREC_FP64, fake, None, fake, 1 << 16)
+    sv.aos_to_soa(v2)
+    with pytest.raises(sv.SphvError):
+        sv.sph_density(v2, cells, p, fake)
+    for x in (v, v2):
+        sv.soa_to_aos(x)
+        sv.view_destroy(x)
+    sv.cells_destroy(cells)
+    with pytest.raises(sv.SphvError) as e:
+        sv.cells_create(10, p, fake + 8, cws)
+    assert e.value.status == sv.E_WORKSPACE
