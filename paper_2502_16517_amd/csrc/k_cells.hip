@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
 {
     __shared__ int lds[kSortWaves][kSortLds];
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     int* buf = lds[w];
     int64_t wave_id = (int64_t)blockIdx.x * kSortWaves + w;
     int64_t nwaves = (int64_t)gridDim.x * kSortWaves;

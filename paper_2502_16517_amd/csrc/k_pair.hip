@@ -67,48 +67,67 @@ __device__ __forceinline__ void neumaier(float& s, float& c, float x)
     s = t;
 }
 
-// Cubic M4 spline and its q-derivative (support q < 2), double and float.
-__device__ __forceinline__ void spline(double q, double& w, double& dw)
+// Cubic M4 spline in its truncated-power form, branch free:
+//   w(q)  = (2-q)_+^3 / 4 - (1-q)_+^3      (= 1 - 1.5 q^2 + 0.75 q^3 below 1)
+//   w'(q) = 3 (1-q)_+^2 - 0.75 (2-q)_+^2
+// Both vanish identically for q >= 2, so no select is needed at the support
+// edge and the two pieces never diverge inside a wave.
+template <class R>
+__device__ __forceinline__ void spline(R q, R& w, R& dw)
 {
-    if (q < 1.0) {
-        double q2 = q * q;
-        w = fma(q2, fma(0.75, q, -1.5), 1.0);
-        dw = q * fma(2.25, q, -3.0);
-    } else {
-        double t = 2.0 - q;
-        double t2 = t * t;
-        w = 0.25 * t2 * t;
-        dw = -0.75 * t2;
-    }
+    const R a = fmax(R(2) - q, R(0));
+    const R b = fmax(R(1) - q, R(0));
+    const R a2 = a * a;
+    const R b2 = b * b;
+    w = fma(R(0.25) * a2, a, -(b2 * b));
+    dw = fma(R(3), b2, R(-0.75) * a2);
 }
 
-__device__ __forceinline__ void spline(float q, float& w, float& dw)
+template <class R>
+__device__ __forceinline__ R spline_dw(R q)
 {
-    if (q < 1.0f) {
-        float q2 = q * q;
-        w = fmaf(q2, fmaf(0.75f, q, -1.5f), 1.0f);
-        dw = q * fmaf(2.25f, q, -3.0f);
-    } else {
-        float t = 2.0f - q;
-        float t2 = t * t;
-        w = 0.25f * t2 * t;
-        dw = -0.75f * t2;
-    }
+    const R a = fmax(R(2) - q, R(0));
+    const R b = fmax(R(1) - q, R(0));
+    return fma(R(3), b * b, R(-0.75) * (a * a));
 }
 
-__device__ __forceinline__ double spline_dw(double q)
+// 1/sqrt(x) for normal x > 0: the hardware estimate refined by Newton-Raphson
+// steps y <- y (3/2 - x y^2 / 2) (two in double, one in float).
+__device__ __forceinline__ double rsqrt_nr(double x)
 {
-    if (q < 1.0) return q * fma(2.25, q, -3.0);
-    double t = 2.0 - q;
-    return q < 2.0 ? -0.75 * t * t : 0.0;
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
 }
 
-__device__ __forceinline__ float spline_dw(float q)
+__device__ __forceinline__ float rsqrt_nr(float x)
 {
-    if (q < 1.0f) return q * fmaf(2.25f, q, -3.0f);
-    float t = 2.0f - q;
-    return q < 2.0f ? -0.75f * t * t : 0.0f;
+    float y = __builtin_amdgcn_rsqf(x);
+    const float hx = 0.5f * x;
+    return y * fmaf(-hx, y * y, 1.5f);
 }
+
+// 1/d: hardware estimate refined by Newton-Raphson steps y <- y + y (1 - d y).
+__device__ __forceinline__ double rcp_nr(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ float rcp_nr(float d)
+{
+    float y = __builtin_amdgcn_rcpf(d);
+    return fmaf(y, fmaf(-d, y, 1.0f), y);
+}
+
+template <class R> struct Tiny;
+template <> struct Tiny<double> { static constexpr double v = 1e-300; };
+template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
 
 // Per-axis reach of a cell, guarded against windows that wrap onto themselves.
 __device__ __forceinline__ void axis_reach(const PairArgs& a, int R, int r[3])
@@ -228,7 +247,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
     for (;;) {
         if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, qoff);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
         __syncthreads();
         if (item < 0) break;
 
@@ -297,37 +316,57 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 sj[lane] = j;
             };
 
+            // one candidate's contribution at the current h; in == false turns
+            // it into the neutral element (zero w and w' add nothing)
+            auto term = [&](int t, R r2, bool in, R& p0, R& p1, R& p2) {
+                const R r = r2 * rsqrt_nr(fmax(r2, Tiny<R>::v));
+                const R q = r * hin;
+                R w, dw;
+                spline(q, w, dw);
+                w = in ? w : (R)0;
+                dw = in ? dw : (R)0;
+                const R m = sm[t];
+                p0 = fma(m, w, p0);
+                p1 = p1 + w;
+                p2 = fma(m, fma(q, dw, (R)3 * w), p2);
+                // the self pair (r = 0) enters the sums but is not counted
+                cnt += (in && (r2 > (R)0 || sj[t] != pi)) ? 1 : 0;
+            };
+
             auto compute = [&](int count) {
                 if (done) return;
                 R p0 = 0, p1 = 0, p2 = 0;
-                for (int t = sl; t < count; t += tpi) {
-                    const R dx = xi - sx[t];
-                    const R dy = yi - sy[t];
-                    const R dz = zi - sz[t];
-                    const R r2 = dx * dx + dy * dy + dz * dz;
-                    const bool in = r2 < H2;
-                    if constexpr (MASKED) {
-                        const R q = sqrt(r2) * hin;
-                        R w, dw;
-                        spline(q, w, dw);
-                        w = in ? w : (R)0;
-                        dw = in ? dw : (R)0;
-                        const R m = sm[t];
-                        p0 = fma(m, w, p0);
-                        p1 = p1 + w;
-                        p2 = fma(m, fma(q, dw, (R)3 * w), p2);
-                        cnt += (in && sj[t] != pi) ? 1 : 0;
-                    } else {
-                        if (in) {
-                            const R q = sqrt(r2) * hin;
-                            R w, dw;
-                            spline(q, w, dw);
-                            const R m = sm[t];
-                            p0 = fma(m, w, p0);
-                            p1 = p1 + w;
-                            p2 = fma(m, fma(q, dw, (R)3 * w), p2);
-                            cnt += sj[t] != pi ? 1 : 0;
-                        }
+                if constexpr (MASKED) {
+                    // every candidate evaluated, out-of-range terms are the neutral element
+                    for (int t = sl; t < count; t += tpi) {
+                        const R dx = xi - sx[t];
+                        const R dy = yi - sy[t];
+                        const R dz = zi - sz[t];
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        term(t, r2, r2 < H2, p0, p1, p2);
+                    }
+                } else {
+                    // test every candidate of this lane, then evaluate only the hits,
+                    // in the same increasing order
+                    uint64_t hits = 0;
+                    int k = 0;
+#pragma unroll 4
+                    for (int t = sl; t < count; t += tpi, ++k) {
+                        const R dx = xi - sx[t];
+                        const R dy = yi - sy[t];
+                        const R dz = zi - sz[t];
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        hits |= (r2 < H2 ? 1ull : 0ull) << k;
+                    }
+                    while (hits) {
+                        const int kk = __builtin_ctzll(hits);
+                        hits &= hits - 1;
+                        const int t = sl + kk * tpi;
+                        const R dx = xi - sx[t];
+                        const R dy = yi - sy[t];
+                        const R dz = zi - sz[t];
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        term(t, r2, true, p0, p1, p2);
                     }
                 }
                 if constexpr (FP32) {
@@ -438,7 +477,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
     using R = typename std::conditional<FP32, float, double>::type;
     // staged j data
     __shared__ R sx[kWave], sy[kWave], sz[kWave], svx[kWave], svy[kWave], svz[kWave];
-    __shared__ R sm[kWave], sh[kWave], shinv[kWave], snorm[kWave], srho[kWave], sA[kWave], sc[kWave], sal[kWave];
+    __shared__ R sm[kWave], sH2[kWave], shinv[kWave], snorm[kWave], srho[kWave], sA[kWave], sc[kWave], sal[kWave];
     __shared__ int sj[kWave];
     __shared__ double red[4][kWave];
     __shared__ double redv[kWave];
@@ -459,7 +498,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
     for (;;) {
         if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, qoff);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
         __syncthreads();
         if (item < 0) break;
 
@@ -509,6 +548,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
         const R hinvi = (R)1 / hi;
         const R hinv2 = hinvi * hinvi;
         const R normi = hinv2 * hinv2 / (R)kPi;
+        const R hali = (R)0.5 * ali;
 
         double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0;
         float fax = 0.f, cax = 0.f, fay = 0.f, cay = 0.f, faz = 0.f, caz = 0.f, fdu = 0.f, cdu = 0.f;
@@ -532,7 +572,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
                 svy[lane] = ld_as_f32(a.f[SPHV_VY], lj, a.g, kj);
                 svz[lane] = ld_as_f32(a.f[SPHV_VZ], lj, a.g, kj);
                 sm[lane] = ld_as_f32(a.f[SPHV_M], lj, a.g, kj);
-                sal[lane] = ld_as_f32(a.f[SPHV_ALPHA], lj, a.g, kj);
+                sal[lane] = (R)0.5 * ld_as_f32(a.f[SPHV_ALPHA], lj, a.g, kj);
                 h_ = ld_as_f32(a.f[SPHV_H], lj, a.g, kj);
                 rho_ = ld_as_f32(a.f[SPHV_RHO], lj, a.g, kj);
                 om_ = ld_as_f32(a.f[SPHV_OMEGA], lj, a.g, kj);
@@ -545,7 +585,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
                 svy[lane] = ld_f64(a.f[SPHV_VY], lj);
                 svz[lane] = ld_f64(a.f[SPHV_VZ], lj);
                 sm[lane] = ld_f64(a.f[SPHV_M], lj);
-                sal[lane] = ld_f64(a.f[SPHV_ALPHA], lj);
+                sal[lane] = (R)0.5 * ld_f64(a.f[SPHV_ALPHA], lj);
                 h_ = ld_f64(a.f[SPHV_H], lj);
                 rho_ = ld_f64(a.f[SPHV_RHO], lj);
                 om_ = ld_f64(a.f[SPHV_OMEGA], lj);
@@ -554,7 +594,8 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
             const R P_ = gm1 * rho_ * u_;
             const R hv = (R)1 / h_;
             const R hv2 = hv * hv;
-            sh[lane] = h_;
+            const R H_ = (R)2 * h_;
+            sH2[lane] = H_ * H_;
             shinv[lane] = hv;
             snorm[lane] = hv2 * hv2 / (R)kPi;
             srho[lane] = rho_;
@@ -563,46 +604,77 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
             sj[lane] = j;
         };
 
+        // (2 max(h_i, h_j))^2 == max((2 h_i)^2, (2 h_j)^2): squaring and its
+        // rounding are monotone, so the test is exact and per side
+        const R Hi = (R)2 * hi;
+        const R H2i = Hi * Hi;
+
+        // one pair's contribution; live == false gives the neutral element
+        auto term = [&](int t, R dx, R dy, R dz, R r2, bool live, R& pax, R& pay, R& paz, R& pdu) {
+            const R y = rsqrt_nr(live ? r2 : (R)1);
+            const R r = r2 * y;
+            const R gi = spline_dw(r * hinvi) * normi;
+            const R gj = spline_dw(r * shinv[t]) * snorm[t];
+            const R gbar = (R)0.5 * (gi + gj);
+            const R ex = dx * y, ey = dy * y, ez = dz * y;
+            const R w = (vxi - svx[t]) * ex + (vyi - svy[t]) * ey + (vzi - svz[t]) * ez;
+            const R mu = w < (R)0 ? w : (R)0;
+            const R vs = ci + sc[t] - (R)3 * mu;
+            // Pi = -(alpha_bar / 2) v_sig mu / rho_bar = -alpha_bar v_sig mu / (rho_i + rho_j)
+            const R visc = -(hali + sal[t]) * vs * mu * rcp_nr(rhoi + srho[t]);
+            const R mj = sm[t];
+            const R Agi = Ai * gi;
+            R coef = mj * fma(visc, gbar, fma(sA[t], gj, Agi));
+            R dui = mj * fma((R)0.5 * visc, gbar, Agi) * w;
+            coef = live ? coef : (R)0;
+            dui = live ? dui : (R)0;
+            pax = fma(-coef, ex, pax);
+            pay = fma(-coef, ey, pay);
+            paz = fma(-coef, ez, paz);
+            pdu = pdu + dui;
+            const R vcand = live ? vs : vsig;
+            vsig = vcand > vsig ? vcand : vsig;
+        };
+
         auto compute = [&](int count) {
             if (!act) return;
             R pax = 0, pay = 0, paz = 0, pdu = 0;
-            for (int t = sl; t < count; t += tpi) {
-                const R dx = xi - sx[t];
-                const R dy = yi - sy[t];
-                const R dz = zi - sz[t];
-                const R r2 = dx * dx + dy * dy + dz * dz;
-                const R hj = sh[t];
-                const R H = (R)2 * (hi > hj ? hi : hj);
-                const bool pair = r2 < H * H && sj[t] != pi;
-                const bool live = pair && r2 > (R)0;
-                cnt += pair ? 1 : 0;
-                if constexpr (!MASKED) {
-                    if (!live) continue;
+            if constexpr (MASKED) {
+                for (int t = sl; t < count; t += tpi) {
+                    const R dx = xi - sx[t];
+                    const R dy = yi - sy[t];
+                    const R dz = zi - sz[t];
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const bool pair = r2 < fmax(H2i, sH2[t]) && (r2 > (R)0 || sj[t] != pi);
+                    cnt += pair ? 1 : 0;
+                    term(t, dx, dy, dz, r2, pair && r2 > (R)0, pax, pay, paz, pdu);
                 }
-                const R r2s = live ? r2 : (R)1;
-                const R r = sqrt(r2s);
-                const R rinv = (R)1 / r;
-                const R gi = spline_dw(r * hinvi) * normi;
-                const R gj = spline_dw(r * shinv[t]) * snorm[t];
-                const R gbar = (R)0.5 * (gi + gj);
-                const R ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                const R w = (vxi - svx[t]) * ex + (vyi - svy[t]) * ey + (vzi - svz[t]) * ez;
-                const R mu = w < (R)0 ? w : (R)0;
-                const R vs = ci + sc[t] - (R)3 * mu;
-                const R visc = (R)(-0.5) * ((R)0.5 * (ali + sal[t])) * vs * mu / ((R)0.5 * (rhoi + srho[t]));
-                const R mj = sm[t];
-                R coef = mj * (Ai * gi + sA[t] * gj + visc * gbar);
-                R dui = mj * (Ai * gi + (R)0.5 * visc * gbar) * w;
-                if constexpr (MASKED) {
-                    coef = live ? coef : (R)0;
-                    dui = live ? dui : (R)0;
+            } else {
+                uint64_t hits = 0;
+                int k = 0;
+#pragma unroll 4
+                for (int t = sl; t < count; t += tpi, ++k) {
+                    const R dx = xi - sx[t];
+                    const R dy = yi - sy[t];
+                    const R dz = zi - sz[t];
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    hits |= (r2 < fmax(H2i, sH2[t]) ? 1ull : 0ull) << k;
                 }
-                pax = fma(-coef, ex, pax);
-                pay = fma(-coef, ey, pay);
-                paz = fma(-coef, ez, paz);
-                pdu = pdu + dui;
-                const R vcand = live ? vs : vsig;
-                vsig = vcand > vsig ? vcand : vsig;
+                while (hits) {
+                    const int kk = __builtin_ctzll(hits);
+                    hits &= hits - 1;
+                    const int t = sl + kk * tpi;
+                    const R dx = xi - sx[t];
+                    const R dy = yi - sy[t];
+                    const R dz = zi - sz[t];
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 > (R)0) {
+                        ++cnt;
+                        term(t, dx, dy, dz, r2, true, pax, pay, paz, pdu);
+                    } else {
+                        cnt += sj[t] != pi ? 1 : 0;   // coincident neighbour: counted, no force
+                    }
+                }
             }
             if constexpr (FP32) {
                 neumaier(fax, cax, pax);
@@ -768,7 +840,7 @@ int pair_grid_blocks(int64_t max_items)
 {
     // persistent grid: enough single-wave workgroups to fill 256 CUs several
     // times over, a multiple of the 8 XCDs
-    int64_t b = 256 * 16;
+    int64_t b = 256 * 20;
     if (max_items < b) b = (max_items + kNumXcd - 1) / kNumXcd * kNumXcd;
     if (b < kNumXcd) b = kNumXcd;
     return (int)b;

@@ -1,0 +1,176 @@
+"""GPU checks of whole steps: kick/drift bit-exact against the oracle (first and
+later steps), graph replay bit-identical to eager steps, layouts bit-identical
+over several steps, conservation over steps, and parity at the full sizes of
+the five workloads on sampled particles."""
+import numpy as np
+import pytest
+
+from paper_2502_16517_amd import inputs
+from paper_2502_16517_amd import sphview as sv
+
+from gpu_helpers import S, bits, check_density, check_force, cols
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_kick_drift_bit_exact_two_steps(orc):
+    w = inputs.two_state_tube(16, 3)
+    p = sv.params_for(w)
+    st = sv.Stepper(w.rec, p)
+    dt_prev = 0.0
+    for step in range(2):
+        st.build()
+        st.density()
+        st.force()
+        before = st.records()
+        state = st.read_state()
+        st.kick()
+        after = st.records()
+        ref = before.copy()
+        orc.kick_drift(ref, S, state.dt, dt_prev, step == 0, w.lo, w.length, w.periodic)
+        assert np.array_equal(bits(ref), bits(after)), step
+        assert state.dt_prev == dt_prev
+        dt_prev = state.dt
+    st.close()
+
+
+def _stream_stepper(w, lay=None, precision=sv.PREC_FP64):
+    s = torch.cuda.Stream()
+    p = sv.params_for(w)
+    if precision == sv.PREC_FP32:
+        p.h_tol = 1e-6
+    return sv.Stepper(w.rec, p, precision, layout_density=lay, layout_force=lay, stream=s), s
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_FP64, sv.PREC_FP32])
+def test_graph_replay_matches_eager(orc, precision):
+    w = inputs.two_state_tube(16, 5)
+    a, sa = _stream_stepper(w, precision=precision)
+    for _ in range(4):
+        a.step()
+    ra, sta = a.records(), a.read_state()
+    a.close()
+    b, sb = _stream_stepper(w, precision=precision)
+    sv.graph_begin(sb)
+    b.step()
+    g = sv.graph_end(sb)
+    torch.cuda.synchronize()
+    junk = torch.zeros(1 << 20, device="cuda")
+    for k in range(4):
+        sv.graph_launch(g, sb)
+        # the program's own eager work and synchronisation between replays
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+        if k == 1:
+            mid = b.read_state()
+            assert mid.nstep == 2
+    rb, stb = b.records(), b.read_state()
+    sv.graph_destroy(g)
+    b.close()
+    assert np.array_equal(bits(ra), bits(rb))
+    assert sta.nstep == stb.nstep == 4
+    assert sta.dt == stb.dt and tuple(sta.sums) == tuple(stb.sums)
+    assert sta.pairs_total == stb.pairs_total
+
+
+def test_multistep_layouts_bit_identical(orc):
+    # 24^3 + 12^3: 9 cells across y and z leave room for h to grow over steps
+    w = inputs.two_state_tube(24, 9)
+    out = {}
+    for name, lay in (("soa", sv.layout()), ("aosoa16", sv.layout(sv.LAYOUT_AOSOA, 16)),
+                      ("direct", sv.layout(sv.LAYOUT_DIRECT)), ("masked", sv.layout(masked=1))):
+        st = sv.Stepper(w.rec, sv.params_for(w), layout_density=lay, layout_force=lay)
+        for _ in range(5):
+            st.step()
+        out[name] = (st.records(), st.read_state())
+        st.close()
+    ref = out["soa"]
+    for name, (r, s) in out.items():
+        assert np.array_equal(bits(r), bits(ref[0])), name
+        assert s.flags == 0 and s.dt == ref[1].dt, name
+
+
+def test_conservation_over_steps(orc):
+    w = inputs.two_state_tube(24, 4)
+    st = sv.Stepper(w.rec, sv.params_for(w))
+    E = []
+    for _ in range(20):
+        st.step()
+        s = st.read_state()
+        assert s.flags == 0
+        E.append(s.sums[3])
+        m_scale = float(np.sum(w.rec[:, S["m"]]))
+        # total momentum stays at roundoff (the start is at rest)
+        assert max(abs(s.sums[k]) for k in range(3)) < 1e-12 * m_scale
+    st.close()
+    assert abs(E[-1] / E[0] - 1) < 1e-4
+
+
+# ------------------------------------------------------------ full sizes
+
+FULL = {
+    "tube64": (lambda: inputs.config2(), {}),
+    "kh128": (lambda: inputs.config3(), {}),
+    "plummer1M": (lambda: inputs.config4(), {"headroom": 1.6}),
+    "kh256": (lambda: inputs.config5(), {}),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_sampled_parity(orc, name):
+    """At the workloads' full sizes, in the launch configuration the benchmark
+    times: every output of a sample of particles against the oracle, which
+    evaluates those particles one by one over the whole particle set."""
+    print(f"[full] {name}", flush=True)
+    mk, pkw = FULL[name]
+    w = mk()
+    p = sv.params_for(w, **pkw)
+    st = sv.Stepper(w.rec, p)
+    st.build()
+    st.density()
+    dens = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    assert state.flags & ~sv.F_OUT_OF_BOX == 0, state.flags
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(w.n, size=400, replace=False))
+    c = cols(w.rec)
+    box = orc.box_of(w.lo, w.length, w.periodic)
+    rd = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, targets=idx)
+    wd = check_density(dens, rd, idx=idx, tol=1e-12)
+    dc = cols(dens)
+    rf = orc.force(dc["x"], dc["y"], dc["z"], dc["vx"], dc["vy"], dc["vz"], dc["m"], dc["h"], dc["rho"],
+                   dc["omega"], dc["u"], dc["alpha"], box, inputs.GAMMA, targets=idx)
+    wf = check_force(out, rf, idx=idx, tol=1e-12, vsig_tol=1e-14)
+    # the sample's pairs per particle agree with the whole step's mean
+    assert abs(rd["count"].mean() / (state.pairs_density / w.n) - 1) < 0.1
+    print(name, "density", wd, "force", wf, "pairs", state.pairs_density, state.pairs_force, flush=True)
+
+
+def test_fp32_full_size_errors(orc):
+    """The precision form on the 128^3 shear layer: per-field error of the FP32
+    pair arithmetic against the FP64 oracle on a sample."""
+    w = inputs.config3()
+    p = sv.params_for(w, h_tol=1e-6)
+    st = sv.Stepper(w.rec, p, sv.PREC_FP32)
+    st.build()
+    st.density()
+    dens = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    assert state.flags == 0
+    idx = np.sort(np.random.default_rng(2).choice(w.n, size=400, replace=False))
+    c = cols(w.rec)
+    box = orc.box_of(w.lo, w.length, w.periodic)
+    rd = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, targets=idx)
+    wd = check_density(dens, rd, idx=idx, tol=1e-5)
+    dc = cols(dens)
+    rf = orc.force(dc["x"], dc["y"], dc["z"], dc["vx"], dc["vy"], dc["vz"], dc["m"], dc["h"], dc["rho"],
+                   dc["omega"], dc["u"], dc["alpha"], box, inputs.GAMMA, targets=idx)
+    wf = check_force(out, rf, idx=idx, tol=1e-4, vsig_tol=1e-6)
+    print("fp32 kh128 density", wd, "force", wf, flush=True)
