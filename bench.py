@@ -60,7 +60,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         g = sv.graph_end(s)
         torch.cuda.synchronize()
     before = st.read_state()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -71,6 +71,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
             continue
         sv.begin_step(st.state, s)
         sv.cells_build(st.cells, st.aos, st.d_cells, st.state, s)
+        ev[k][4].record(s)
         sv.aos_to_soa(st.v_dens, st.cells, s)
         ev[k][0].record(s)
         sv.sph_density(st.v_dens, st.cells, st.p, st.state, s)
@@ -82,6 +83,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         ev[k][3].record(s)
         sv.step_reduce(st.v_force, st.p, st.state, s)
         sv.soa_to_aos(st.v_force, s)
+        ev[k][5].record(s)
         sv.kick_drift(st.aos, st.d_kick, st.n, st.p, st.state, s)
     e_end.record(s)
     torch.cuda.synchronize()
@@ -93,6 +95,8 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
     if not graph:
         res["ms_density"] = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
         res["ms_force"] = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+        # the span of the two views: first density gather to last force scatter
+        res["ms_span"] = sum(e[4].elapsed_time(e[5]) for e in ev) / steps
     if g is not None:
         sv.graph_destroy(g)
     return res
@@ -148,6 +152,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-traffic kernel for "
+                         "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how "
@@ -163,6 +170,15 @@ def main():
     # one side stream (default priority) for everything: graph capture needs a
     # stream other than the legacy null stream, and events record on it
     torch.cuda.set_stream(torch.cuda.Stream())
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
     log("[bench] generating the two-state tube (294,912 particles)")
     w = inputs.config2()
     lay = sv.layout(sv.LAYOUT_SOA)
@@ -187,7 +203,7 @@ def main():
         r32 = run_timed(torch, sv, st, args.steps, args.warmup)
         st.close()
         f32 = {"value": r32["pairs"] / (r32["ms_total"] / 1e3), "ms_per_step": r32["ms_total"] / args.steps,
-               "ms_density": r32["ms_density"], "ms_force": r32["ms_force"],
+               "ms_density": r32["ms_density"], "ms_force": r32["ms_force"], "ms_span": r32["ms_span"],
                "speedup_vs_fp64": (r32["pairs"] / r32["ms_total"]) / (r64["pairs"] / r64["ms_total"])}
 
     ms_step = r64["ms_total"] / args.steps
@@ -234,6 +250,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "graph": {"value": g64["pairs"] / (g64["ms_total"] / 1e3), "ms_per_step": g64["ms_total"] / args.steps},
+        # pairs/s over the two views alone (gathers, loops, reduction, scatters),
+        # without cells_build and kick_drift
+        "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
         "hbm_frac_step": None,
     }

@@ -310,6 +310,45 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state_dev, vo
 int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
                         const sphv_params* p, const void* state_dev, void* stream);
 
+/* ------------------------------------------------------------- autotuner */
+
+/* Per-loop choice of layout and tile shape (the batching layer's tuner: which
+ * layout pays differs per kernel in the paper's measurements, Sec. 7, Table 2
+ * and Sec. 7.5).
+ * A candidate is an sphv_layout; one trial times, with HIP events on stream,
+ * the gather of A_in, the loop and the scatter of A_out of a view with that
+ * layout, over the records aos_dev (described by d, indexed by the cells'
+ * perm), starting from the records as they are.  Each candidate runs reps
+ * trials; its figure is their median.  The fastest candidate is written to
+ * *best and the medians, in candidate order, to ms (NULL: not reported).
+ *
+ * candidates: NULL for the built-in set (sphv_autotune_candidates), else an
+ *   array of n_candidates (1..64) layouts.
+ * Records: every member d names is copied out bit for bit before the first
+ *   trial and copied back after each trial and at the end, so the records
+ *   leave the call as they came in.  Run it on records that hold a valid
+ *   state for the loop (for the force loop: after a density scatter).
+ * ws_dev: device workspace of sphv_autotune_workspace_bytes(...) bytes, 256-B
+ *   aligned (state block, bit copy of the members, the largest candidate view).
+ * The call synchronises stream (it times on the host) and fails with
+ * SPHV_E_STATE while stream is being captured into a graph, SPHV_E_ALIAS if an
+ * open view on the same records conflicts with a trial view, SPHV_E_WORKSPACE
+ * for a small or misaligned workspace.  Every kernel exits normally on every
+ * candidate; flags of the trials go to the private state block, not the
+ * caller's.  Cells are left built; the density mask cache keeps the last
+ * trial's contents, which the next density call rewrites. */
+enum { SPHV_LOOP_DENSITY = 0, SPHV_LOOP_FORCE = 1 };
+
+/* Writes up to cap built-in candidates to out (NULL: none), returns their count. */
+int32_t sphv_autotune_candidates(sphv_layout* out, int32_t cap);
+/* 0 on invalid arguments. */
+size_t sphv_autotune_workspace_bytes(const sphv_descriptor* d, int64_t n, int32_t precision,
+                                     const sphv_layout* candidates, int32_t n_candidates);
+int32_t sphv_autotune(int32_t loop, void* aos_dev, const sphv_descriptor* d, const sphv_cells* cells,
+                      const sphv_params* p, int32_t precision, const sphv_layout* candidates,
+                      int32_t n_candidates, int32_t reps, void* ws_dev, size_t ws_bytes,
+                      sphv_layout* best, float* ms, void* stream);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* Capture everything enqueued on stream between begin and end into a HIP graph

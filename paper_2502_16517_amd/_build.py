@@ -13,7 +13,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphview.so")
 ARCH = os.environ.get("SPHV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "k_cells.hip", "k_view.hip", "k_pair.hip"]
+SOURCES = ["abi.cpp", "tune.cpp", "k_cells.hip", "k_view.hip", "k_pair.hip"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -257,6 +257,7 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
     c->tmp_b = (int32_t*)take(4 * (uint64_t)nc);
     c->item_start = (int32_t*)take(4 * (uint64_t)(nc + 1));
     c->items = (int4*)take(16 * (uint64_t)max_items);
+    c->item_masks = (uint64_t*)take(8ull * kMaskChunks * kWave * (uint64_t)max_items);
     c->scan_part = (int32_t*)take(4 * (uint64_t)scan_blocks);
     c->meta = (int32_t*)take(4 * META_SIZE);
     c->n = n;
@@ -651,6 +652,8 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     a->items = c->dev.items;
     a->cell_start = c->dev.cell_start;
     a->key_sorted = c->dev.key_sorted;
+    a->reach_d = c->dev.reach_d;
+    a->item_masks = c->dev.item_masks;
     a->meta = c->dev.meta;
     a->state = (DevState*)state;
     a->eta = p->eta;

@@ -13,6 +13,7 @@ constexpr int kMaxFields = 32;
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRedBlock = 1024;  // particles per block of the fixed-order reductions
+constexpr int kMaskChunks = 12;  // candidate chunks per work item whose hit masks are cached
 
 // Device state block (mirrors sphv_state field for field).
 struct DevState {
@@ -75,6 +76,7 @@ struct CellsDev {
     int32_t* tmp_b;        // [nc]
     int32_t* item_start;   // [nc + 1]
     int4* items;           // [max_items]  (cell, first sorted pos, count, 0)
+    uint64_t* item_masks;  // [max_items][kMaskChunks][64] candidate hit masks of the density loop
     int32_t* scan_part;    // [scan blocks + 1]
     int32_t* meta;         // [64]: 0 n_items, 1 R_global, 2.. queue heads/exits
     int64_t n;
@@ -90,6 +92,7 @@ enum {
     META_QEXIT_D = 16,
     META_QHEAD_F = 24,
     META_QEXIT_F = 32,
+    META_MASKS = 40,     // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
     META_SIZE = 64
 };
 
@@ -102,6 +105,8 @@ struct PairArgs {
     const int32_t* cell_start;
     const int32_t* reach;      // density or force reach
     const int32_t* key_sorted; // cell of sorted position p
+    const int32_t* reach_d;    // density reach (the force loop compares it with its own)
+    uint64_t* item_masks;      // cached candidate masks (see CellsDev)
     int32_t* meta;             // queue counters
     int32_t qhead, qexit;      // meta slots of this kernel's queue
     DevState* state;

@@ -146,13 +146,15 @@ __device__ __forceinline__ void axis_reach(const PairArgs& a, int R, int r[3])
 // Walk the window of cell (kx,ky,kz): every contiguous span of candidates with
 // its periodic image (ix,iy,iz in {-1,0,1}), staged 64 at a time into LDS slot
 // 'lane'.  stage(j, ix, iy, iz) is called by the lane that owns the slot;
-// compute(count) runs between barriers once 64 candidates (or the rest) are in.
+// compute(count, chunk) runs between barriers once 64 candidates (or the rest)
+// are in; chunk numbers the batches 0, 1, ... in this fixed order.
 template <class Stage, class Compute>
 __device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], int lane,
                                            Stage&& stage, Compute&& compute)
 {
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
     int fill = 0;
+    int chunk = 0;
     for (int dz = -r[2]; dz <= r[2]; ++dz) {
         int z2 = kz + dz, iz = 0;
         if (z2 < 0 || z2 >= nz) {
@@ -168,34 +170,34 @@ __device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, in
                 y2 -= iy * ny;
             }
             const int row = (z2 * ny + y2) * nx;
-            int x0 = kx - r[0], x1 = kx + r[0];
+            const int x0 = kx - r[0], x1 = kx + r[0];
+            const bool per = a.g.periodic[0] != 0;
             // up to three spans: wrapped left part, main part, wrapped right part
-            int sc0[3], sc1[3], six[3], ns = 0;
-            if (a.g.periodic[0]) {
-                if (x0 < 0) { sc0[ns] = x0 + nx; sc1[ns] = nx - 1; six[ns] = -1; ++ns; x0 = 0; }
-                int xr = x1 >= nx ? nx - 1 : x1;
-                sc0[ns] = x0; sc1[ns] = xr; six[ns] = 0; ++ns;
-                if (x1 >= nx) { sc0[ns] = 0; sc1[ns] = x1 - nx; six[ns] = 1; ++ns; }
-            } else {
-                sc0[0] = x0 < 0 ? 0 : x0;
-                sc1[0] = x1 >= nx ? nx - 1 : x1;
-                six[0] = 0;
-                ns = 1;
-            }
-            for (int sgi = 0; sgi < ns; ++sgi) {
-                int jb = a.cell_start[row + sc0[sgi]];
-                const int je = a.cell_start[row + sc1[sgi] + 1];
+            for (int sgi = 0; sgi < 3; ++sgi) {
+                int c0, c1, ix;
+                if (sgi == 0) {
+                    if (!(per && x0 < 0)) continue;
+                    c0 = x0 + nx; c1 = nx - 1; ix = -1;
+                } else if (sgi == 1) {
+                    c0 = x0 < 0 ? 0 : x0; c1 = x1 >= nx ? nx - 1 : x1; ix = 0;
+                } else {
+                    if (!(per && x1 >= nx)) continue;
+                    c0 = 0; c1 = x1 - nx; ix = 1;
+                }
+                int jb = a.cell_start[row + c0];
+                const int je = a.cell_start[row + c1 + 1];
                 while (jb < je) {
                     int take = je - jb;
                     if (take > kWave - fill) take = kWave - fill;
-                    if (lane >= fill && lane < fill + take) stage(jb + lane - fill, six[sgi], iy, iz);
+                    if (lane >= fill && lane < fill + take) stage(jb + lane - fill, ix, iy, iz);
                     fill += take;
                     jb += take;
                     if (fill == kWave) {
                         __syncthreads();
-                        compute(kWave);
+                        compute(kWave, chunk);
                         __syncthreads();
                         fill = 0;
+                        ++chunk;
                     }
                 }
             }
@@ -203,9 +205,222 @@ __device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, in
     }
     if (fill) {
         __syncthreads();
-        compute(fill);
+        compute(fill, chunk);
         __syncthreads();
     }
+}
+
+// Raw members of one staged candidate (as loaded, before conversion).
+template <class T, int K>
+struct RawK {
+    T v[K];
+    int j, ix, iy, iz, key;
+    uint64_t mask;
+};
+template <class T> using Raw4 = RawK<T, 4>;
+template <class T> using Raw12 = RawK<T, 12>;
+
+template <class T, class L>
+__device__ __forceinline__ T ld_raw(const FieldRef& f, const L& l)
+{
+    return *(const T*)l.at(f);
+}
+
+// Float coordinate relative to the corner of cell k along axis d: an FP32
+// view stores it already; a record's double is converted exactly as the
+// gather converts it.
+__device__ __forceinline__ float rel32_of(float v, int, int, const Geom&) { return v; }
+__device__ __forceinline__ float rel32_of(double v, int d, int k, const Geom& g)
+{
+    const double o = __dadd_rn(g.lo[d], __dmul_rn((double)k, g.cell[d]));
+    return __double2float_rn(__dsub_rn(v, o));
+}
+
+// ------------------------------------------------------------------ spans
+//
+// The window of a work item as a table of spans built once per item: every
+// (dy, dz) row contributes up to three contiguous spans of sorted positions
+// (wrapped left part, main part, wrapped right part), in the order for_window
+// visits them, so candidate q of the window (and chunk q / 64) is the same
+// in both.  Rows are resolved by all lanes at once, and the staging of chunk
+// c + 1 is issued before chunk c is evaluated.
+
+constexpr int kMaxSpans = 160;     // windows of reach <= 3 (7 x 7 rows x 3 spans)
+constexpr int kMaxChunksW = 128;   // candidates per window <= 8192
+constexpr int kSpanPosBits = 27;   // sorted positions below 2^27 share a word with the image
+
+struct SpanLds {
+    uint32_t jbi[kMaxSpans];      // first sorted position of the span | image << 27, the periodic
+                                  // image (ix+1) + 3 (iy+1) + 9 (iz+1) < 27
+    uint16_t pre[kMaxSpans + 2];  // window index of its first candidate; pre[ns] = W
+    uint8_t cstart[kMaxChunksW];  // span holding the first candidate of each chunk
+};
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total)
+{
+    int x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+}
+
+// Fills L for the window of cell (kx, ky, kz) with per-axis reach r; returns
+// false (for every lane) when the window exceeds the table, leaving the
+// caller to walk it with for_window.
+__device__ bool build_spans(const PairArgs& a, int kx, int ky, int kz, const int r[3], int lane, SpanLds& L,
+                            int& ns_out, int& W_out)
+{
+    if (a.n >= (1ll << kSpanPosBits)) return false;
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    const int nyw = 2 * r[1] + 1;
+    const int nrows = nyw * (2 * r[2] + 1);
+    int ns = 0, W = 0;
+    for (int r0 = 0; r0 < nrows; r0 += kWave) {
+        const int rr = r0 + lane;
+        // the row's spans in window order: wrapped left part, main part, wrapped
+        // right part (each may be absent)
+        int cnt = 0;
+        int b0 = 0, n0 = 0, b1 = 0, n1 = 0, b2 = 0, n2 = 0;
+        bool vl = false, vr = false;
+        uint32_t img = 0;
+        if (rr < nrows) {
+            int z2 = kz + rr / nyw - r[2], iz = 0;
+            int y2 = ky + rr % nyw - r[1], iy = 0;
+            bool ok = true;
+            if (z2 < 0 || z2 >= nz) {
+                if (a.g.periodic[2]) { iz = z2 < 0 ? -1 : 1; z2 -= iz * nz; } else ok = false;
+            }
+            if (y2 < 0 || y2 >= ny) {
+                if (a.g.periodic[1]) { iy = y2 < 0 ? -1 : 1; y2 -= iy * ny; } else ok = false;
+            }
+            if (ok) {
+                const int row = (z2 * ny + y2) * nx;
+                const int x0 = kx - r[0], x1 = kx + r[0];
+                const bool per = a.g.periodic[0] != 0;
+                vl = per && x0 < 0;
+                vr = per && x1 >= nx;
+                const int m0 = x0 < 0 ? 0 : x0;
+                const int m1 = x1 >= nx ? nx - 1 : x1;
+                if (vl) {
+                    b0 = a.cell_start[row + x0 + nx];
+                    n0 = a.cell_start[row + nx] - b0;
+                }
+                b1 = a.cell_start[row + m0];
+                n1 = a.cell_start[row + m1 + 1] - b1;
+                if (vr) {
+                    b2 = a.cell_start[row];
+                    n2 = a.cell_start[row + x1 - nx + 1] - b2;
+                }
+                cnt = 1 + (vl ? 1 : 0) + (vr ? 1 : 0);
+                img = (uint32_t)(3 * (iy + 1) + 9 * (iz + 1));
+            }
+        }
+        int tot_s, tot_w;
+        const int ps = wave_excl_scan(cnt, lane, tot_s);
+        const int pw = wave_excl_scan(n0 + n1 + n2, lane, tot_w);
+        if (ns + tot_s > kMaxSpans || W + tot_w >= 65536) return false;
+        if (cnt) {
+            int k = ns + ps;
+            int w = W + pw;
+            if (vl) {
+                L.jbi[k] = (uint32_t)b0 | (img << kSpanPosBits);
+                L.pre[k] = (uint16_t)w;
+                ++k;
+                w += n0;
+            }
+            L.jbi[k] = (uint32_t)b1 | ((img + 1u) << kSpanPosBits);
+            L.pre[k] = (uint16_t)w;
+            ++k;
+            w += n1;
+            if (vr) {
+                L.jbi[k] = (uint32_t)b2 | ((img + 2u) << kSpanPosBits);
+                L.pre[k] = (uint16_t)w;
+            }
+        }
+        ns += tot_s;
+        W += tot_w;
+    }
+    const int nch = (W + kWave - 1) / kWave;
+    if (nch > kMaxChunksW) return false;
+    if (lane == 0) L.pre[ns] = (uint16_t)W;
+    __syncthreads();
+    for (int c = lane; c < nch; c += kWave) {
+        // the last span starting at or before the chunk's first candidate
+        const int q = c * kWave;
+        int lo = 0, hi = ns;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (L.pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        L.cstart[c] = (uint8_t)lo;
+    }
+    __syncthreads();
+    ns_out = ns;
+    W_out = W;
+    return true;
+}
+
+// Candidate q of chunk c for this lane: its sorted position and image.
+__device__ __forceinline__ void span_lookup(const SpanLds& L, int c, int q, int& j, int& ix, int& iy, int& iz)
+{
+    int s = L.cstart[c];
+    while (L.pre[s + 1] <= q) ++s;
+    const uint32_t v = L.jbi[s];
+    j = (int)(v & ((1u << kSpanPosBits) - 1u)) + (q - L.pre[s]);
+    const int im = (int)(v >> kSpanPosBits);
+    ix = im % 3 - 1;
+    iy = (im / 3) % 3 - 1;
+    iz = im / 9 - 1;
+}
+
+// Pipelined walk of a window described by L: fetch(valid, j, ix, iy, iz, c)
+// issues the loads of this lane's candidate of chunk c and returns them,
+// put(v, in_chunk) writes them to this lane's LDS slot, compute(count, chunk)
+// evaluates a staged chunk.  The loads of chunk c + 1 are in flight while
+// chunk c is evaluated.
+template <class Fetch, class Put, class Compute>
+__device__ __forceinline__ void run_window(const SpanLds& L, int W, int lane, Fetch&& fetch, Put&& put,
+                                           Compute&& compute)
+{
+    const int nch = (W + kWave - 1) / kWave;
+    auto get = [&](int c) {
+        const int q = c * kWave + lane;
+        int j = 0, ix = 0, iy = 0, iz = 0;
+        const bool valid = q < W;
+        if (valid) span_lookup(L, c, q, j, ix, iy, iz);
+        return fetch(valid, j, ix, iy, iz, c);
+    };
+    auto cur = get(0);
+    for (int c = 0; c < nch; ++c) {
+        const int count = W - c * kWave < kWave ? W - c * kWave : kWave;
+        put(cur, lane < count);
+        if (c + 1 < nch) cur = get(c + 1);
+        __syncthreads();
+        compute(count, c);
+        __syncthreads();
+    }
+}
+
+// Bit k of the result is test(sl + k*tpi) for the candidates of this lane
+// below count; four tests are packed per step.
+template <class Test>
+__device__ __forceinline__ uint64_t lane_mask(int count, int sl, int tpi, Test&& test)
+{
+    uint64_t hits = 0;
+    int k = 0;
+    int t = sl;
+    for (; t + 3 * tpi < count; t += 4 * tpi, k += 4) {
+        const uint32_t b0 = test(t) ? 1u : 0u;
+        const uint32_t b1 = test(t + tpi) ? 2u : 0u;
+        const uint32_t b2 = test(t + 2 * tpi) ? 4u : 0u;
+        const uint32_t b3 = test(t + 3 * tpi) ? 8u : 0u;
+        hits |= (uint64_t)(b0 | b1 | b2 | b3) << k;
+    }
+    for (; t < count; t += tpi, ++k) hits |= (test(t) ? 1ull : 0ull) << k;
+    return hits;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -224,21 +439,103 @@ __device__ __forceinline__ int wave_max_i(int v)
 }
 
 // ================================================================ density
+//
+// Window-resident neighbour lists.  A first walk over a work item's window
+// tests every candidate against a list radius per local particle, 2 h_l with
+// h_l = min(h_cap, (1 + 1/16) h), and keeps the union of the hits (over the
+// item's particles) compacted in LDS, position and mass, and per particle the
+// list of its hits as indices into that union.  Every pass of the h iteration
+// then walks its particle's list, split evenly over the particle's lanes,
+// without touching global memory or the window again.  Should a Newton step
+// take some h beyond its h_l, the item starts over with the chunk walk below;
+// so does a window whose union or lists do not fit.  The chunk walk restages
+// the window 64 candidates at a time in every pass and revisits the hits
+// within twice the cell cap that its first pass cached.
+// The walk that builds the lists also writes those cap hits for the force loop.
+
+constexpr int kUMax = 256;     // union entries per work item (list entries are bytes)
+constexpr int kPool = 2304;    // list entries per work item, split evenly over its particles
+constexpr double kListGrow = 1.0 + 1.0 / 16.0;
+
+template <class R>
+struct alignas(16) P4 {
+    R x, y, z, m;
+};
+
+template <class R>
+union DensStage {
+    struct {
+        R x[kWave], y[kWave], z[kWave], m[kWave];
+        int j[kWave];
+    } s;                       // one chunk of staged candidates
+    struct {
+        double t[3][kWave];
+        int c[kWave];
+    } r;                       // per-lane partial sums of a pass
+};
+
+template <class R>
+union DensBig {
+    uint64_t mcache[kMaskChunks][kWave];   // chunk walk: hit masks of the first pass
+    P4<R> u[kUMax];                        // list walk: the union of the hits
+};
+
+// Bit k of lo (hi) is set when candidate sl + k*tpi lies within r2lo (r2hi);
+// r^2 is fused, four candidates are tested per step.
+template <class R>
+__device__ __forceinline__ void lane_mask2(const R* sx, const R* sy, const R* sz, int count, int sl, int tpi, R xi,
+                                           R yi, R zi, R r2lo, R r2hi, uint64_t& lo, uint64_t& hi)
+{
+    auto r2f = [&](int t) {
+        const R dx = xi - sx[t];
+        const R dy = yi - sy[t];
+        const R dz = zi - sz[t];
+        return fma(dz, dz, fma(dy, dy, dx * dx));
+    };
+    lo = 0;
+    hi = 0;
+    int k = 0;
+    int t = sl;
+    for (; t + 3 * tpi < count; t += 4 * tpi, k += 4) {
+        const R q0 = r2f(t), q1 = r2f(t + tpi), q2 = r2f(t + 2 * tpi), q3 = r2f(t + 3 * tpi);
+        const uint32_t l = (q0 < r2lo ? 1u : 0u) | (q1 < r2lo ? 2u : 0u) | (q2 < r2lo ? 4u : 0u) |
+                           (q3 < r2lo ? 8u : 0u);
+        const uint32_t h = (q0 < r2hi ? 1u : 0u) | (q1 < r2hi ? 2u : 0u) | (q2 < r2hi ? 4u : 0u) |
+                           (q3 < r2hi ? 8u : 0u);
+        lo |= (uint64_t)l << k;
+        hi |= (uint64_t)h << k;
+    }
+    for (; t < count; t += tpi, ++k) {
+        const R q = r2f(t);
+        lo |= (q < r2lo ? 1ull : 0ull) << k;
+        hi |= (q < r2hi ? 1ull : 0ull) << k;
+    }
+}
 
 template <bool DIRECT, bool FP32, bool MASKED>
 __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
 {
     using R = typename std::conditional<FP32, float, double>::type;
-    __shared__ R sx[kWave], sy[kWave], sz[kWave], sm[kWave];
-    __shared__ int sj[kWave];
-    __shared__ double red[3][kWave];
-    __shared__ int redc[kWave];
+    using RawT = typename std::conditional<FP32 && !DIRECT, float, double>::type;
+    __shared__ DensStage<R> st;
+    __shared__ SpanLds spans;
+    __shared__ DensBig<R> big;
+    __shared__ uint8_t s_list[kPool];
+    __shared__ uint8_t s_uidx[kWave];
+    __shared__ uint8_t s_flag[kWave];
+    __shared__ int s_self[kWave];
     __shared__ int s_item;
+    R* const sx = st.s.x;
+    R* const sy = st.s.y;
+    R* const sz = st.s.z;
+    R* const sm = st.s.m;
+    int* const sj = st.s.j;
 
     const int lane = threadIdx.x;
     const int n_items = a.meta[META_NITEMS];
     const int xcd = blockIdx.x % kNumXcd;
     const double eta3 = a.eta * a.eta * a.eta;
+    if (!MASKED && blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 1 + a.tpi + (FP32 ? 128 : 0);
     int qoff = 0;
     unsigned long long n_final = 0, n_evals = 0;
     int maxit = 0;
@@ -265,6 +562,12 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
         double hcap = 0.5 * (double)r[0] * a.g.cell[0];
         hcap = fmin(hcap, 0.5 * (double)r[1] * a.g.cell[1]);
         hcap = fmin(hcap, 0.5 * (double)r[2] * a.g.cell[2]);
+        // no h of this item can exceed hcap, so no pair of any pass lies beyond 2 hcap
+        const double Hcap = 2.0 * hcap;
+        // widened so that a fused r^2 (a few ulp from the exact one) never misses a
+        // candidate: the exact test decides each pair later
+        constexpr double kWiden = FP32 ? 1.0 + 4e-6 : 1.0 + 1e-12;
+        const R H2capw = (R)(Hcap * Hcap * kWiden);
 
         const Loc<DIRECT> li = locate<DIRECT>(a.acc, pi);
         R xi, yi, zi;
@@ -280,9 +583,127 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
             zi = ld_f64(a.f[SPHV_Z], li);
             mi = ld_f64(a.f[SPHV_M], li);
         }
-        double h = ld_f64(a.f[SPHV_H], li);
-        bool done = !act;
+        const double h0 = ld_f64(a.f[SPHV_H], li);
+        // list radius of this particle (its h may not leave [.., hl] while the lists serve it)
+        const double hl = fmin(hcap, kListGrow * h0);
+        const R Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
+        int n_spans = 0, W = 0;
+        const bool use_spans = build_spans(a, kx, ky, kz, r, lane, spans, n_spans, W);
 
+        // staging of one candidate: fetch issues the loads (raw members), put
+        // converts them and writes this lane's LDS slot
+        auto fetch = [&](bool valid, int j, int ix, int iy, int iz, int) {
+            Raw4<RawT> v;
+            v.j = j;
+            v.ix = ix;
+            v.iy = iy;
+            v.iz = iz;
+            if (valid) {
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                v.v[0] = ld_raw<RawT>(a.f[SPHV_X], lj);
+                v.v[1] = ld_raw<RawT>(a.f[SPHV_Y], lj);
+                v.v[2] = ld_raw<RawT>(a.f[SPHV_Z], lj);
+                v.v[3] = ld_raw<RawT>(a.f[SPHV_M], lj);
+                if constexpr (FP32) v.key = a.key_sorted[j];
+            }
+            return v;
+        };
+        auto put = [&](const Raw4<RawT>& v, bool in_chunk) {
+            if (!in_chunk) return;
+            if constexpr (FP32) {
+                int jx, jy, jz;
+                cell_coords(v.key, a.g, jx, jy, jz);
+                sx[lane] = rel32_of(v.v[0], 0, jx, a.g) +
+                           __double2float_rn((double)(jx - kx + v.ix * a.g.n[0]) * a.g.cell[0]);
+                sy[lane] = rel32_of(v.v[1], 1, jy, a.g) +
+                           __double2float_rn((double)(jy - ky + v.iy * a.g.n[1]) * a.g.cell[1]);
+                sz[lane] = rel32_of(v.v[2], 2, jz, a.g) +
+                           __double2float_rn((double)(jz - kz + v.iz * a.g.n[2]) * a.g.cell[2]);
+                sm[lane] = (R)v.v[3];
+            } else {
+                sx[lane] = v.v[0] + (double)v.ix * a.g.len[0];
+                sy[lane] = v.v[1] + (double)v.iy * a.g.len[1];
+                sz[lane] = v.v[2] + (double)v.iz * a.g.len[2];
+                sm[lane] = v.v[3];
+            }
+            sj[lane] = v.j;
+        };
+        auto stage = [&](int j, int ix, int iy, int iz) { put(fetch(true, j, ix, iy, iz, 0), true); };
+
+        // ---- list walk set-up: one walk over the window builds the union and the lists
+        const int cap_i = kPool / ni;      // list entries per particle
+        const int lbase = (act ? il : 0) * cap_i;
+        int len = 0;                        // entries of this particle's list
+        bool lists = false;
+        if (use_spans) {
+            s_self[lane] = -1;
+            const int nch = (W + kWave - 1) / kWave;
+            const int g0 = act ? il * tpi : 0;
+            const int g1 = act ? g0 + tpi - 1 : 0;
+            int nU = 0;
+            bool fits = true;
+            auto get = [&](int c) {
+                const int q = c * kWave + lane;
+                int j = 0, ix = 0, iy = 0, iz = 0;
+                const bool valid = q < W;
+                if (valid) span_lookup(spans, c, q, j, ix, iy, iz);
+                return fetch(valid, j, ix, iy, iz, c);
+            };
+            auto cur = get(0);
+            for (int c = 0; c < nch && fits; ++c) {
+                const int count = W - c * kWave < kWave ? W - c * kWave : kWave;
+                put(cur, lane < count);
+                s_flag[lane] = 0;
+                if (c + 1 < nch) cur = get(c + 1);
+                __syncthreads();
+                uint64_t hits = 0, caph = 0;
+                if (act) lane_mask2<R>(sx, sy, sz, count, sl, tpi, xi, yi, zi, Hl2w, H2capw, hits, caph);
+                if (!MASKED && c < kMaskChunks)
+                    a.item_masks[((int64_t)item * kMaskChunks + c) * kWave + lane] = caph;
+                for (uint64_t m = hits; m; m &= m - 1) s_flag[sl + __builtin_ctzll(m) * tpi] = 1;
+                __syncthreads();
+                // compact the chunk's hits (over all particles) into the union
+                const bool f = lane < count && s_flag[lane];
+                const uint64_t bal = __ballot(f);
+                const int u = nU + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                nU += __popcll(bal);
+                if (f && u < kUMax) {
+                    big.u[u] = P4<R>{sx[lane], sy[lane], sz[lane], sm[lane]};
+                    s_uidx[lane] = (uint8_t)u;
+                }
+                // append this lane's hits to its particle's list, lanes in order
+                const int hl_n = __popcll(hits);
+                int tot;
+                const int excl = wave_excl_scan(hl_n, lane, tot);
+                const int e0 = __shfl(excl, g0, kWave);
+                const int e1 = __shfl(excl + hl_n, g1, kWave);
+                const int pos = len + excl - e0;
+                const bool over = nU > kUMax || (act && pos + hl_n > cap_i);
+                fits = !__any(over);
+                __syncthreads();
+                if (fits) {
+                    int k = pos;
+                    for (uint64_t m = hits; m; m &= m - 1) {
+                        const int t = sl + __builtin_ctzll(m) * tpi;
+                        const int u2 = s_uidx[t];
+                        s_list[lbase + k] = (uint8_t)u2;
+                        ++k;
+                        if (sj[t] == pi) s_self[il] = u2;
+                    }
+                    len += e1 - e0;
+                }
+                __syncthreads();
+            }
+            lists = fits;
+        }
+        const int self_u = lists && act ? s_self[il] : -1;
+
+        double h = h0;
+        bool done = !act;
+        unsigned long long it_final = 0, it_evals = 0;
+        int it_maxit = 0;
+        uint32_t it_flags = 0;
         for (int pass = 0;; ++pass) {
             const double Hd = 2.0 * h;
             const double H2d = Hd * Hd;
@@ -294,81 +715,20 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
             float f0 = 0.f, f1 = 0.f, f2 = 0.f;         // FP32 running sums
             int cnt = 0;
 
-            auto stage = [&](int j, int ix, int iy, int iz) {
-                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                if constexpr (FP32) {
-                    const int kj = a.key_sorted[j];
-                    int jx, jy, jz;
-                    cell_coords(kj, a.g, jx, jy, jz);
-                    const int dkx = jx - kx + ix * a.g.n[0];
-                    const int dky = jy - ky + iy * a.g.n[1];
-                    const int dkz = jz - kz + iz * a.g.n[2];
-                    sx[lane] = ld_as_f32(a.f[SPHV_X], lj, a.g, kj) + __double2float_rn((double)dkx * a.g.cell[0]);
-                    sy[lane] = ld_as_f32(a.f[SPHV_Y], lj, a.g, kj) + __double2float_rn((double)dky * a.g.cell[1]);
-                    sz[lane] = ld_as_f32(a.f[SPHV_Z], lj, a.g, kj) + __double2float_rn((double)dkz * a.g.cell[2]);
-                    sm[lane] = ld_as_f32(a.f[SPHV_M], lj, a.g, kj);
-                } else {
-                    sx[lane] = ld_f64(a.f[SPHV_X], lj) + (double)ix * a.g.len[0];
-                    sy[lane] = ld_f64(a.f[SPHV_Y], lj) + (double)iy * a.g.len[1];
-                    sz[lane] = ld_f64(a.f[SPHV_Z], lj) + (double)iz * a.g.len[2];
-                    sm[lane] = ld_f64(a.f[SPHV_M], lj);
-                }
-                sj[lane] = j;
-            };
-
             // one candidate's contribution at the current h; in == false turns
             // it into the neutral element (zero w and w' add nothing)
-            auto term = [&](int t, R r2, bool in, R& p0, R& p1, R& p2) {
-                const R r = r2 * rsqrt_nr(fmax(r2, Tiny<R>::v));
-                const R q = r * hin;
+            auto term = [&](R m, R r2, bool in, R& p0, R& p1, R& p2) {
+                const R rr = r2 * rsqrt_nr(fmax(r2, Tiny<R>::v));
+                const R q = rr * hin;
                 R w, dw;
                 spline(q, w, dw);
                 w = in ? w : (R)0;
                 dw = in ? dw : (R)0;
-                const R m = sm[t];
                 p0 = fma(m, w, p0);
                 p1 = p1 + w;
                 p2 = fma(m, fma(q, dw, (R)3 * w), p2);
-                // the self pair (r = 0) enters the sums but is not counted
-                cnt += (in && (r2 > (R)0 || sj[t] != pi)) ? 1 : 0;
             };
-
-            auto compute = [&](int count) {
-                if (done) return;
-                R p0 = 0, p1 = 0, p2 = 0;
-                if constexpr (MASKED) {
-                    // every candidate evaluated, out-of-range terms are the neutral element
-                    for (int t = sl; t < count; t += tpi) {
-                        const R dx = xi - sx[t];
-                        const R dy = yi - sy[t];
-                        const R dz = zi - sz[t];
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        term(t, r2, r2 < H2, p0, p1, p2);
-                    }
-                } else {
-                    // test every candidate of this lane, then evaluate only the hits,
-                    // in the same increasing order
-                    uint64_t hits = 0;
-                    int k = 0;
-#pragma unroll 4
-                    for (int t = sl; t < count; t += tpi, ++k) {
-                        const R dx = xi - sx[t];
-                        const R dy = yi - sy[t];
-                        const R dz = zi - sz[t];
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        hits |= (r2 < H2 ? 1ull : 0ull) << k;
-                    }
-                    while (hits) {
-                        const int kk = __builtin_ctzll(hits);
-                        hits &= hits - 1;
-                        const int t = sl + kk * tpi;
-                        const R dx = xi - sx[t];
-                        const R dy = yi - sy[t];
-                        const R dz = zi - sz[t];
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        term(t, r2, true, p0, p1, p2);
-                    }
-                }
+            auto fold = [&](R p0, R p1, R p2) {
                 if constexpr (FP32) {
                     neumaier(f0, c0, p0);
                     neumaier(f1, c1, p1);
@@ -380,7 +740,84 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 }
             };
 
-            for_window(a, kx, ky, kz, r, lane, stage, compute);
+            if (lists) {
+                if (!done) {
+                    // entries sl, sl + tpi, ... of the list; float partial sums are
+                    // folded into the compensated ones every 16 entries
+                    R p0 = 0, p1 = 0, p2 = 0;
+                    int k = 0;
+                    for (int e = sl; e < len; e += tpi) {
+                        const int u = s_list[lbase + e];
+                        const P4<R> c = big.u[u];
+                        const R dx = xi - c.x;
+                        const R dy = yi - c.y;
+                        const R dz = zi - c.z;
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        const bool in = r2 < H2;
+                        if (MASKED || in) term(c.m, r2, in, p0, p1, p2);
+                        cnt += (in && u != self_u) ? 1 : 0;
+                        if (FP32 && ++k == 16) {
+                            fold(p0, p1, p2);
+                            p0 = p1 = p2 = 0;
+                            k = 0;
+                        }
+                    }
+                    fold(p0, p1, p2);
+                }
+            } else {
+                auto compute = [&](int count, int chunk) {
+                    if (done) return;
+                    R p0 = 0, p1 = 0, p2 = 0;
+                    if constexpr (MASKED) {
+                        // every candidate evaluated, out-of-range terms are the neutral element
+                        for (int t = sl; t < count; t += tpi) {
+                            const R dx = xi - sx[t];
+                            const R dy = yi - sy[t];
+                            const R dz = zi - sz[t];
+                            const R r2 = dx * dx + dy * dy + dz * dz;
+                            const bool in = r2 < H2;
+                            term(sm[t], r2, in, p0, p1, p2);
+                            // the self pair (r = 0) enters the sums but is not counted
+                            cnt += (in && (r2 > (R)0 || sj[t] != pi)) ? 1 : 0;
+                        }
+                    } else {
+                        // the first pass tests every candidate of this lane against 2 hcap
+                        // and keeps the hits; later passes only revisit those.  Hits are
+                        // evaluated in increasing order, in range at the current h only.
+                        uint64_t hits = 0;
+                        if (pass > 0 && chunk < kMaskChunks) {
+                            hits = big.mcache[chunk][lane];
+                        } else {
+                            hits = lane_mask(count, sl, tpi, [&](int t) {
+                                const R dx = xi - sx[t];
+                                const R dy = yi - sy[t];
+                                const R dz = zi - sz[t];
+                                return fma(dz, dz, fma(dy, dy, dx * dx)) < H2capw;
+                            });
+                            if (pass == 0 && chunk < kMaskChunks) {
+                                big.mcache[chunk][lane] = hits;
+                                a.item_masks[((int64_t)item * kMaskChunks + chunk) * kWave + lane] = hits;
+                            }
+                        }
+                        while (hits) {
+                            const int kk = __builtin_ctzll(hits);
+                            hits &= hits - 1;
+                            const int t = sl + kk * tpi;
+                            const R dx = xi - sx[t];
+                            const R dy = yi - sy[t];
+                            const R dz = zi - sz[t];
+                            const R r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 < H2) {
+                                term(sm[t], r2, true, p0, p1, p2);
+                                cnt += (r2 > (R)0 || sj[t] != pi) ? 1 : 0;
+                            }
+                        }
+                    }
+                    fold(p0, p1, p2);
+                };
+                if (use_spans) run_window(spans, W, lane, fetch, put, compute);
+                else for_window(a, kx, ky, kz, r, lane, stage, compute);
+            }
 
             if constexpr (FP32) {
                 t0 = (double)f0 + (double)c0;
@@ -388,25 +825,26 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 t2 = (double)f2 + (double)c2;
             }
             if (tpi > 1) {
-                red[0][lane] = t0;
-                red[1][lane] = t1;
-                red[2][lane] = t2;
-                redc[lane] = cnt;
+                st.r.t[0][lane] = t0;
+                st.r.t[1][lane] = t1;
+                st.r.t[2][lane] = t2;
+                st.r.c[lane] = cnt;
                 __syncthreads();
                 if (act) {
                     const int b = il * tpi;
                     t0 = t1 = t2 = 0.0;
                     cnt = 0;
                     for (int k = 0; k < tpi; ++k) {
-                        t0 += red[0][b + k];
-                        t1 += red[1][b + k];
-                        t2 += red[2][b + k];
-                        cnt += redc[b + k];
+                        t0 += st.r.t[0][b + k];
+                        t1 += st.r.t[1][b + k];
+                        t2 += st.r.t[2][b + k];
+                        cnt += st.r.c[b + k];
                     }
                 }
                 __syncthreads();
             }
 
+            bool leave = false;   // an h outgrew its list radius
             if (!done) {
                 const double h3 = h * h * h;
                 const double norm = 1.0 / (kPi * h3);
@@ -427,30 +865,47 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 if (!isfinite(hn)) hn = a.eta * cbrt(mi / rho);
                 if (hn > hcap) {
                     hn = hcap;
-                    flags |= SPHV_F_H_CAP_HIT;
+                    it_flags |= SPHV_F_H_CAP_HIT;
                 }
                 const bool conv = fabs(hn - h) <= a.tol * h;
-                if (sl == 0) n_evals += (unsigned long long)cnt;
+                if (sl == 0) it_evals += (unsigned long long)cnt;
                 if (conv || pass + 1 >= a.max_iter) {
-                    if (!conv) flags |= SPHV_F_H_NOT_CONVERGED;
+                    if (!conv) it_flags |= SPHV_F_H_NOT_CONVERGED;
                     const double omega = 1.0 + h / (3.0 * rho) * drho;
                     const double wcount = (4.0 * kPi / 3.0) * (8.0 * h3) * nsum;
-                    if (!(isfinite(rho) && isfinite(omega))) flags |= SPHV_F_NONFINITE_OUTPUT;
+                    if (!(isfinite(rho) && isfinite(omega))) it_flags |= SPHV_F_NONFINITE_OUTPUT;
                     if (sl == 0) {
                         st_f64(a.f[SPHV_H], li, h);
                         st_f64(a.f[SPHV_RHO], li, rho);
                         st_f64(a.f[SPHV_OMEGA], li, omega);
                         st_f64(a.f[SPHV_WCOUNT], li, wcount);
-                        n_final += (unsigned long long)cnt;
+                        it_final += (unsigned long long)cnt;
                     }
-                    maxit = pass + 1 > maxit ? pass + 1 : maxit;
+                    it_maxit = pass + 1 > it_maxit ? pass + 1 : it_maxit;
                     done = true;
                 } else {
+                    leave = lists && hn > hl;
                     h = hn;
                 }
             }
+            if (__any(leave)) {
+                // start the item over with the chunk walk: its results replace
+                // whatever the list walk stored
+                lists = false;
+                h = h0;
+                done = !act;
+                it_final = it_evals = 0;
+                it_maxit = 0;
+                it_flags = 0;
+                pass = -1;
+                continue;
+            }
             if (__all(done)) break;
         }
+        n_final += it_final;
+        n_evals += it_evals;
+        maxit = it_maxit > maxit ? it_maxit : maxit;
+        flags |= it_flags;
     }
 
     n_final = wave_sum_u64(n_final);
@@ -478,6 +933,8 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
     // staged j data
     __shared__ R sx[kWave], sy[kWave], sz[kWave], svx[kWave], svy[kWave], svz[kWave];
     __shared__ R sm[kWave], sH2[kWave], shinv[kWave], snorm[kWave], srho[kWave], sA[kWave], sc[kWave], sal[kWave];
+    __shared__ SpanLds spans;
+    using RawT = typename std::conditional<FP32 && !DIRECT, float, double>::type;
     __shared__ int sj[kWave];
     __shared__ double red[4][kWave];
     __shared__ double redv[kWave];
@@ -490,6 +947,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
     const R gm = (R)a.gamma;
     const R gm1 = (R)(a.gamma - 1.0);
     const R ggm1 = (R)(a.gamma * (a.gamma - 1.0));
+    const int masks_tag = a.meta[META_MASKS];
     int qoff = 0;
     unsigned long long n_pairs = 0;
     uint32_t flags = 0;
@@ -513,6 +971,11 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
         cell_coords(cell, a.g, kx, ky, kz);
         int r[3];
         axis_reach(a, a.reach[cell], r);
+        // same window as the density loop and the same lanes per particle: its
+        // cached candidate masks apply
+        const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && a.reach[cell] == a.reach_d[cell];
+        int n_spans = 0, W = 0;
+        const bool use_spans = build_spans(a, kx, ky, kz, r, lane, spans, n_spans, W);
 
         // local particle i and its derived quantities
         const Loc<DIRECT> li = locate<DIRECT>(a.acc, pi);
@@ -555,42 +1018,50 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
         R vsig = (R)2 * ci;
         int cnt = 0;
 
-        auto stage = [&](int j, int ix, int iy, int iz) {
-            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-            R u_, rho_, om_, h_;
-            if constexpr (FP32) {
-                const int kj = a.key_sorted[j];
-                int jx, jy, jz;
-                cell_coords(kj, a.g, jx, jy, jz);
-                const int dkx = jx - kx + ix * a.g.n[0];
-                const int dky = jy - ky + iy * a.g.n[1];
-                const int dkz = jz - kz + iz * a.g.n[2];
-                sx[lane] = ld_as_f32(a.f[SPHV_X], lj, a.g, kj) + __double2float_rn((double)dkx * a.g.cell[0]);
-                sy[lane] = ld_as_f32(a.f[SPHV_Y], lj, a.g, kj) + __double2float_rn((double)dky * a.g.cell[1]);
-                sz[lane] = ld_as_f32(a.f[SPHV_Z], lj, a.g, kj) + __double2float_rn((double)dkz * a.g.cell[2]);
-                svx[lane] = ld_as_f32(a.f[SPHV_VX], lj, a.g, kj);
-                svy[lane] = ld_as_f32(a.f[SPHV_VY], lj, a.g, kj);
-                svz[lane] = ld_as_f32(a.f[SPHV_VZ], lj, a.g, kj);
-                sm[lane] = ld_as_f32(a.f[SPHV_M], lj, a.g, kj);
-                sal[lane] = (R)0.5 * ld_as_f32(a.f[SPHV_ALPHA], lj, a.g, kj);
-                h_ = ld_as_f32(a.f[SPHV_H], lj, a.g, kj);
-                rho_ = ld_as_f32(a.f[SPHV_RHO], lj, a.g, kj);
-                om_ = ld_as_f32(a.f[SPHV_OMEGA], lj, a.g, kj);
-                u_ = ld_as_f32(a.f[SPHV_U], lj, a.g, kj);
-            } else {
-                sx[lane] = ld_f64(a.f[SPHV_X], lj) + (double)ix * a.g.len[0];
-                sy[lane] = ld_f64(a.f[SPHV_Y], lj) + (double)iy * a.g.len[1];
-                sz[lane] = ld_f64(a.f[SPHV_Z], lj) + (double)iz * a.g.len[2];
-                svx[lane] = ld_f64(a.f[SPHV_VX], lj);
-                svy[lane] = ld_f64(a.f[SPHV_VY], lj);
-                svz[lane] = ld_f64(a.f[SPHV_VZ], lj);
-                sm[lane] = ld_f64(a.f[SPHV_M], lj);
-                sal[lane] = (R)0.5 * ld_f64(a.f[SPHV_ALPHA], lj);
-                h_ = ld_f64(a.f[SPHV_H], lj);
-                rho_ = ld_f64(a.f[SPHV_RHO], lj);
-                om_ = ld_f64(a.f[SPHV_OMEGA], lj);
-                u_ = ld_f64(a.f[SPHV_U], lj);
+        // staging of one candidate: fetch issues the loads (raw members and, when
+        // the density loop's masks apply, this lane's mask of the chunk), put
+        // converts them, derives P, c, A, 1/h, and writes this lane's LDS slot
+        uint64_t cmask = 0;
+        auto fetch = [&](bool valid, int j, int ix, int iy, int iz, int c) {
+            Raw12<RawT> v;
+            v.j = j;
+            v.ix = ix;
+            v.iy = iy;
+            v.iz = iz;
+            v.mask = 0;
+            if (reuse && c < kMaskChunks) v.mask = a.item_masks[((int64_t)item * kMaskChunks + c) * kWave + lane];
+            if (valid) {
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                const int roles[12] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_M, SPHV_ALPHA,
+                                       SPHV_H, SPHV_RHO, SPHV_OMEGA, SPHV_U};
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v.v[k] = ld_raw<RawT>(a.f[roles[k]], lj);
+                if constexpr (FP32) v.key = a.key_sorted[j];
             }
+            return v;
+        };
+        auto put = [&](const Raw12<RawT>& v, bool in_chunk) {
+            cmask = v.mask;
+            if (!in_chunk) return;
+            if constexpr (FP32) {
+                int jx, jy, jz;
+                cell_coords(v.key, a.g, jx, jy, jz);
+                const int dk[3] = {jx - kx + v.ix * a.g.n[0], jy - ky + v.iy * a.g.n[1], jz - kz + v.iz * a.g.n[2]};
+                const int kk[3] = {jx, jy, jz};
+                R* dst[3] = {sx, sy, sz};
+                for (int d = 0; d < 3; ++d)
+                    dst[d][lane] = rel32_of(v.v[d], d, kk[d], a.g) + __double2float_rn((double)dk[d] * a.g.cell[d]);
+            } else {
+                sx[lane] = v.v[0] + (double)v.ix * a.g.len[0];
+                sy[lane] = v.v[1] + (double)v.iy * a.g.len[1];
+                sz[lane] = v.v[2] + (double)v.iz * a.g.len[2];
+            }
+            svx[lane] = (R)v.v[3];
+            svy[lane] = (R)v.v[4];
+            svz[lane] = (R)v.v[5];
+            sm[lane] = (R)v.v[6];
+            sal[lane] = (R)0.5 * (R)v.v[7];
+            const R h_ = (R)v.v[8], rho_ = (R)v.v[9], om_ = (R)v.v[10], u_ = (R)v.v[11];
             const R P_ = gm1 * rho_ * u_;
             const R hv = (R)1 / h_;
             const R hv2 = hv * hv;
@@ -601,13 +1072,17 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
             srho[lane] = rho_;
             sA[lane] = P_ / (om_ * rho_ * rho_);
             sc[lane] = sqrt(ggm1 * u_);
-            sj[lane] = j;
+            sj[lane] = v.j;
         };
+        auto stage = [&](int j, int ix, int iy, int iz) { put(fetch(true, j, ix, iy, iz, kMaskChunks), true); };
 
         // (2 max(h_i, h_j))^2 == max((2 h_i)^2, (2 h_j)^2): squaring and its
         // rounding are monotone, so the test is exact and per side
         const R Hi = (R)2 * hi;
         const R H2i = Hi * Hi;
+        // the candidate test uses a fused r^2, shrunk so that it never rejects a pair
+        // the exact test in the hit loop would accept
+        const R shrink = (R)(FP32 ? 1.0 - 4e-6 : 1.0 - 1e-12);
 
         // one pair's contribution; live == false gives the neutral element
         auto term = [&](int t, R dx, R dy, R dz, R r2, bool live, R& pax, R& pay, R& paz, R& pdu) {
@@ -636,7 +1111,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
             vsig = vcand > vsig ? vcand : vsig;
         };
 
-        auto compute = [&](int count) {
+        auto compute = [&](int count, int chunk) {
             if (!act) return;
             R pax = 0, pay = 0, paz = 0, pdu = 0;
             if constexpr (MASKED) {
@@ -650,15 +1125,19 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
                     term(t, dx, dy, dz, r2, pair && r2 > (R)0, pax, pay, paz, pdu);
                 }
             } else {
+                // candidates of this lane that can be pairs: the density loop's hit
+                // masks when they cover this window (a superset: every force pair lies
+                // within twice the cell cap), else a test of every candidate
                 uint64_t hits = 0;
-                int k = 0;
-#pragma unroll 4
-                for (int t = sl; t < count; t += tpi, ++k) {
-                    const R dx = xi - sx[t];
-                    const R dy = yi - sy[t];
-                    const R dz = zi - sz[t];
-                    const R r2 = dx * dx + dy * dy + dz * dz;
-                    hits |= (r2 < fmax(H2i, sH2[t]) ? 1ull : 0ull) << k;
+                if (reuse && chunk < kMaskChunks) {
+                    hits = use_spans ? cmask : a.item_masks[((int64_t)item * kMaskChunks + chunk) * kWave + lane];
+                } else {
+                    hits = lane_mask(count, sl, tpi, [&](int t) {
+                        const R dx = xi - sx[t];
+                        const R dy = yi - sy[t];
+                        const R dz = zi - sz[t];
+                        return fma(dz, dz, fma(dy, dy, dx * dx)) * shrink < fmax(H2i, sH2[t]);
+                    });
                 }
                 while (hits) {
                     const int kk = __builtin_ctzll(hits);
@@ -668,6 +1147,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
                     const R dy = yi - sy[t];
                     const R dz = zi - sz[t];
                     const R r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < fmax(H2i, sH2[t]))) continue;
                     if (r2 > (R)0) {
                         ++cnt;
                         term(t, dx, dy, dz, r2, true, pax, pay, paz, pdu);
@@ -689,7 +1169,8 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
             }
         };
 
-        for_window(a, kx, ky, kz, r, lane, stage, compute);
+        if (use_spans) run_window(spans, W, lane, fetch, put, compute);
+        else for_window(a, kx, ky, kz, r, lane, stage, compute);
 
         if constexpr (FP32) {
             ax = (double)fax + (double)cax;

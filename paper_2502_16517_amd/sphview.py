@@ -26,6 +26,7 @@ F64, F32, I64, I32 = 1, 2, 3, 4
 IN, OUT, INOUT = 1, 2, 3
 LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
+LOOP_DENSITY, LOOP_FORCE = 0, 1
 
 ROLES = ["user", "x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "ax", "ay", "az", "m", "h", "rho",
          "omega", "u", "uh", "u_dt", "alpha", "v_sig", "wcount"]
@@ -37,7 +38,8 @@ EXPORTS = [
     "sphv_cells_build", "sphv_cells_get_info", "sphv_cells_destroy", "sphv_view_workspace_bytes",
     "sphv_view_create", "sphv_aos_to_soa", "sphv_soa_to_aos", "sphv_view_field", "sphv_view_destroy",
     "sphv_sph_density", "sphv_sph_force", "sphv_step_reduce", "sphv_kick_drift", "sphv_graph_begin", "sphv_graph_end",
-    "sphv_graph_launch", "sphv_graph_destroy",
+    "sphv_graph_launch", "sphv_graph_destroy", "sphv_autotune_candidates", "sphv_autotune_workspace_bytes",
+    "sphv_autotune",
 ]
 
 
@@ -124,6 +126,12 @@ def lib():
         "sphv_graph_end": (C.c_int32, [VP, C.POINTER(VP)]),
         "sphv_graph_launch": (C.c_int32, [VP, VP]),
         "sphv_graph_destroy": (None, [VP]),
+        "sphv_autotune_candidates": (C.c_int32, [C.POINTER(Layout), C.c_int32]),
+        "sphv_autotune_workspace_bytes": (C.c_size_t, [C.POINTER(Descriptor), C.c_int64, C.c_int32,
+                                                       C.POINTER(Layout), C.c_int32]),
+        "sphv_autotune": (C.c_int32, [C.c_int32, VP, C.POINTER(Descriptor), VP, C.POINTER(Params), C.c_int32,
+                                      C.POINTER(Layout), C.c_int32, C.c_int32, VP, C.c_size_t,
+                                      C.POINTER(Layout), C.POINTER(C.c_float), VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -354,6 +362,47 @@ def graph_destroy(g):
     lib().sphv_graph_destroy(g)
 
 
+# ------------------------------------------------------------ autotuner
+
+def autotune_candidates() -> list:
+    """The library's built-in candidate layouts."""
+    k = int(lib().sphv_autotune_candidates(None, 0))
+    arr = (Layout * k)()
+    lib().sphv_autotune_candidates(arr, k)
+    return [Layout(c.kind, c.aosoa_width, c.tpi, c.masked) for c in arr]
+
+
+def _layout_array(cands):
+    if cands is None:
+        return None, 0
+    arr = (Layout * len(cands))(*[Layout(c.kind, c.aosoa_width, c.tpi, c.masked) for c in cands])
+    return arr, len(cands)
+
+
+def autotune_workspace_bytes(d: Descriptor, n: int, precision: int, candidates=None) -> int:
+    arr, k = _layout_array(candidates)
+    return int(lib().sphv_autotune_workspace_bytes(C.byref(d), n, precision, arr, k))
+
+
+def autotune(loop: int, aos, d: Descriptor, cells, p: Params, precision: int, ws, candidates=None, reps: int = 3,
+             stream=None, ws_bytes: int | None = None):
+    """Times every candidate layout for one loop; returns (best Layout, list of
+    (Layout, median ms)) in candidate order."""
+    cands = candidates if candidates is not None else autotune_candidates()
+    arr, k = _layout_array(cands)
+    ms = (C.c_float * k)()
+    best = Layout()
+    nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
+    _chk(lib().sphv_autotune(loop, _ptr(aos), C.byref(d), cells, C.byref(p), precision, arr, k, reps, _ptr(ws), nb,
+                             C.byref(best), ms, _stream(stream)), "autotune")
+    return best, [(c, float(ms[i])) for i, c in enumerate(cands)]
+
+
+def layout_name(l: Layout) -> str:
+    kind = {LAYOUT_SOA: "soa", LAYOUT_AOSOA: f"aosoa{l.aosoa_width}", LAYOUT_DIRECT: "direct"}[l.kind]
+    return f"{kind}/tpi{l.tpi or 'auto'}/{'masked' if l.masked else 'branch'}"
+
+
 # ------------------------------------------------------------ step driver
 
 class Stepper:
@@ -425,6 +474,41 @@ class Stepper:
 
     def read_state(self) -> State:
         return read_state(self.state, self.stream)
+
+    def set_layouts(self, layout_density: Layout | None = None, layout_force: Layout | None = None):
+        """Re-plans the views (no view may be open)."""
+        u8 = dict(dtype=self.torch.uint8, device=self.device)
+        if layout_density is not None:
+            view_destroy(self.v_dens)
+            self.v_dens = None
+            self.ld = layout_density
+            self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_dens, self.n, self.ld,
+                                                                          self.precision)), **u8)
+            self.v_dens = view_create(self.d_dens, self.n, self.ld, self.precision, self.aos, self.perm_ptr,
+                                      self.ws_dens)
+        if layout_force is not None:
+            view_destroy(self.v_force)
+            self.v_force = None
+            self.lf = layout_force
+            self.ws_force = self.torch.empty(max(256, view_workspace_bytes(self.d_force, self.n, self.lf,
+                                                                           self.precision)), **u8)
+            self.v_force = view_create(self.d_force, self.n, self.lf, self.precision, self.aos, self.perm_ptr,
+                                       self.ws_force)
+
+    def autotune(self, candidates=None, reps: int = 3):
+        """Picks the density and the force layouts on the current records (run
+        after at least one step, so the force inputs are valid) and re-plans
+        both views with them.  Returns {"density": (best, table), "force": ...}."""
+        self.build()
+        out = {}
+        for loop, d, key in ((LOOP_DENSITY, self.d_dens, "density"), (LOOP_FORCE, self.d_force, "force")):
+            nb = autotune_workspace_bytes(d, self.n, self.precision, candidates)
+            ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)
+            out[key] = autotune(loop, self.aos, d, self.cells, self.p, self.precision, ws, candidates, reps,
+                                self.stream)
+            del ws
+        self.set_layouts(out["density"][0], out["force"][0])
+        return out
 
     def records(self) -> np.ndarray:
         self.torch.cuda.synchronize()

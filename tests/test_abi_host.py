@@ -198,3 +198,40 @@ def test_loop_calls_need_an_open_view_and_built_cells():
     with pytest.raises(sv.SphvError) as e:
         sv.cells_create(10, p, fake + 8, cws)
     assert e.value.status == sv.E_WORKSPACE
+
+
+def test_autotune_candidates_and_workspace():
+    cands = sv.autotune_candidates()
+    # 6 layouts (SoA, AoSoA 8..64, records) x lanes per particle {auto,1,2,4,8} x {branch, masked}
+    assert len(cands) == 60
+    kinds = {(c.kind, c.aosoa_width) for c in cands}
+    assert kinds == {(sv.LAYOUT_SOA, 0), (sv.LAYOUT_DIRECT, 0)} | {(sv.LAYOUT_AOSOA, w) for w in (8, 16, 32, 64)}
+    assert {c.tpi for c in cands} == {0, 1, 2, 4, 8} and {c.masked for c in cands} == {0, 1}
+    n = 1000
+    for d in (sv.density_descriptor(), sv.force_descriptor()):
+        for prec in (sv.PREC_FP64, sv.PREC_FP32):
+            views = max(sv.view_workspace_bytes(d, n, c, prec) for c in cands)
+            backup = sum(-(-n * 8 // 256) * 256 for _ in range(d.n_fields))
+            assert sv.autotune_workspace_bytes(d, n, prec) == 256 + backup + -(-views // 256) * 256
+            one = [sv.layout(sv.LAYOUT_DIRECT)]
+            assert sv.autotune_workspace_bytes(d, n, prec, one) == 256 + backup + \
+                -(-sv.view_workspace_bytes(d, n, one[0], prec) // 256) * 256
+    assert sv.autotune_workspace_bytes(sv.density_descriptor(), n, sv.PREC_FP64, [sv.layout(tpi=65)]) == 0
+
+
+def test_autotune_argument_errors():
+    fake = 1 << 40
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    cells = sv.cells_create(10, p, fake, sv.cells_workspace_bytes(10, p))
+    d = sv.density_descriptor()
+    need = sv.autotune_workspace_bytes(d, 10, sv.PREC_FP64)
+    for loop, reps, ws, nb, status in ((7, 3, fake, need, sv.E_INVALID_ARG), (0, 0, fake, need, sv.E_INVALID_ARG),
+                                       (0, 3, fake, need - 1, sv.E_WORKSPACE),
+                                       (0, 3, fake + 64, need, sv.E_WORKSPACE)):
+        with pytest.raises(sv.SphvError) as e:
+            sv.autotune(loop, fake, d, cells, p, sv.PREC_FP64, ws, reps=reps, ws_bytes=nb)
+        assert e.value.status == status
+    with pytest.raises(sv.SphvError) as e:
+        sv.autotune(0, fake, d, cells, p, sv.PREC_FP64, fake, candidates=[sv.layout(kind=9)], ws_bytes=need)
+    assert e.value.status == sv.E_INVALID_ARG
+    sv.cells_destroy(cells)
