@@ -97,6 +97,8 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         res["ms_force"] = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
         # the span of the two views: first density gather to last force scatter
         res["ms_span"] = sum(e[4].elapsed_time(e[5]) for e in ev) / steps
+        log("[bench]   per-step density ms " + " ".join(f"{e[0].elapsed_time(e[1]):.3f}" for e in ev))
+        log("[bench]   per-step force ms   " + " ".join(f"{e[2].elapsed_time(e[3]):.3f}" for e in ev))
     if g is not None:
         sv.graph_destroy(g)
     return res

@@ -258,6 +258,7 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
     c->item_start = (int32_t*)take(4 * (uint64_t)(nc + 1));
     c->items = (int4*)take(16 * (uint64_t)max_items);
     c->item_masks = (uint64_t*)take(8ull * kMaskChunks * kWave * (uint64_t)max_items);
+    c->pair_part = (int64_t*)take(8ull * kPartSlots * kMaxPairBlocks);
     c->scan_part = (int32_t*)take(4 * (uint64_t)scan_blocks);
     c->meta = (int32_t*)take(4 * META_SIZE);
     c->n = n;
@@ -655,6 +656,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     a->reach_d = c->dev.reach_d;
     a->item_masks = c->dev.item_masks;
     a->meta = c->dev.meta;
+    a->part = c->dev.pair_part;
     a->state = (DevState*)state;
     a->eta = p->eta;
     a->tol = p->h_tol;
@@ -682,7 +684,6 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     if (v->n == 0) return SPHV_OK;
     a.reach = c->dev.reach_d;
     a.qhead = META_QHEAD_D;
-    a.qexit = META_QEXIT_D;
     return hip_status(launch_density(a, v->layout.kind == SPHV_LAYOUT_DIRECT, v->precision == SPHV_PREC_FP32,
                                      (int)v->layout.masked, (hipStream_t)stream));
 }
@@ -700,7 +701,6 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     if (v->n == 0) return SPHV_OK;
     a.reach = c->dev.reach_f;
     a.qhead = META_QHEAD_F;
-    a.qexit = META_QEXIT_F;
     hipStream_t st = (hipStream_t)stream;
     bool direct = v->layout.kind == SPHV_LAYOUT_DIRECT;
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, st));

@@ -14,6 +14,9 @@ constexpr int kWave = 64;
 constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRedBlock = 1024;  // particles per block of the fixed-order reductions
 constexpr int kMaskChunks = 12;  // candidate chunks per work item whose hit masks are cached
+constexpr int kQStride = 32;     // ints between two queue heads: one 128-byte line each
+constexpr int kMaxPairBlocks = 256 * 20;   // largest grid of a pair loop
+constexpr int kPartSlots = 4;    // per-wave counters a pair loop leaves for its fold
 
 // Device state block (mirrors sphv_state field for field).
 struct DevState {
@@ -77,8 +80,9 @@ struct CellsDev {
     int32_t* item_start;   // [nc + 1]
     int4* items;           // [max_items]  (cell, first sorted pos, count, 0)
     uint64_t* item_masks;  // [max_items][kMaskChunks][64] candidate hit masks of the density loop
+    int64_t* pair_part;    // [kMaxPairBlocks][kPartSlots] per-wave counters of the last pair loop
     int32_t* scan_part;    // [scan blocks + 1]
-    int32_t* meta;         // [64]: 0 n_items, 1 R_global, 2.. queue heads/exits
+    int32_t* meta;         // [META_SIZE]: item count, R_global, mask tag, queue heads
     int64_t n;
     int64_t nc;
     int64_t max_items;
@@ -88,12 +92,10 @@ struct CellsDev {
 enum {
     META_NITEMS = 0,
     META_RGLOBAL = 1,
-    META_QHEAD_D = 8,    // 8 per-XCD heads for the density queue
-    META_QEXIT_D = 16,
-    META_QHEAD_F = 24,
-    META_QEXIT_F = 32,
-    META_MASKS = 40,     // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
-    META_SIZE = 64
+    META_MASKS = 2,                          // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
+    META_QHEAD_D = 64,                       // 8 per-XCD heads of the density queue, kQStride apart
+    META_QHEAD_F = 64 + kNumXcd * kQStride,  // the same for the force queue
+    META_SIZE = 64 + 2 * kNumXcd * kQStride
 };
 
 // Arguments of the pair kernels.
@@ -108,12 +110,13 @@ struct PairArgs {
     const int32_t* reach_d;    // density reach (the force loop compares it with its own)
     uint64_t* item_masks;      // cached candidate masks (see CellsDev)
     int32_t* meta;             // queue counters
-    int32_t qhead, qexit;      // meta slots of this kernel's queue
+    int64_t* part;             // per-wave counters, folded by the launch that follows
+    int32_t qhead, pad2;       // meta slot of this kernel's first queue head
     DevState* state;
     double eta, tol, gamma;
     int32_t max_iter;
     int32_t tpi;               // 0 = automatic
-    int32_t nblocks;           // grid size (for the exit counter)
+    int32_t nblocks;           // grid size (<= kMaxPairBlocks: one counter slot per wave)
     int32_t pad;
     double* red_part;          // force: per reduction block partials
     int64_t n;

@@ -182,7 +182,7 @@ constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
 __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_start, const int32_t* perm_tmp,
                                                           int32_t* perm, int32_t* key_sorted,
                                                           const uint32_t* hmax_bits, int32_t* reach_d,
-                                                          int32_t* item_cnt, int32_t* meta, Geom g, int64_t nc)
+                                                          int32_t* item_cnt, Geom g, int64_t nc)
 {
     __shared__ int lds[kSortWaves][kSortLds];
     const int lane = threadIdx.x & (kWave - 1);
@@ -190,7 +190,6 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
     int* buf = lds[w];
     int64_t wave_id = (int64_t)blockIdx.x * kSortWaves + w;
     int64_t nwaves = (int64_t)gridDim.x * kSortWaves;
-    int rmax = 0;
     for (int64_t c = wave_id; c < nc; c += nwaves) {
         int b = cell_start[c], e = cell_start[c + 1];
         int cnt = e - b;
@@ -236,10 +235,8 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
             }
             reach_d[c] = R;
             item_cnt[c] = (cnt + kWave - 1) / kWave;
-            rmax = R > rmax ? R : rmax;
         }
     }
-    if (lane == 0 && rmax > 0) atomicMax(&meta[META_RGLOBAL], rmax);
 }
 
 __global__ void k_items(const int32_t* cell_start, const int32_t* item_start, int64_t nc, int64_t max_items,
@@ -260,6 +257,27 @@ __global__ void k_items(const int32_t* cell_start, const int32_t* item_start, in
     for (int f = b; f < e; f += kWave) {
         if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 0);
         ++o;
+    }
+}
+
+// R_global = max of the cells' reach: a block maximum each, one atomic per block
+constexpr int kMaxThreads = 1024;
+
+__global__ __launch_bounds__(kMaxThreads) void k_reach_max(const int32_t* reach, int64_t nc, int32_t* meta)
+{
+    __shared__ int s[kMaxThreads / kWave];
+    int m = 0;
+    for (int64_t c = (int64_t)blockIdx.x * kMaxThreads + threadIdx.x; c < nc; c += (int64_t)gridDim.x * kMaxThreads)
+        m = reach[c] > m ? reach[c] : m;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(m, off, kWave);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kMaxThreads / kWave; ++k) m = s[k] > m ? s[k] : m;
+        if (m > 0) atomicMax(&meta[META_RGLOBAL], m);
     }
 }
 
@@ -330,8 +348,13 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     }
     unsigned sb = (unsigned)std::min<int64_t>((c.nc + kSortWaves - 1) / kSortWaves, 8192);
     hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
-                       c.key_sorted, c.hmax_bits, c.reach_d, c.tmp_a, c.meta, g, c.nc);
+                       c.key_sorted, c.hmax_bits, c.reach_d, c.tmp_a, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        const unsigned mb = (unsigned)std::min<int64_t>(std::max<int64_t>((c.nc + kMaxThreads - 1) / kMaxThreads, 1), 64);
+        hipLaunchKernelGGL(k_reach_max, dim3(mb), dim3(kMaxThreads), 0, s, c.reach_d, c.nc, c.meta);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.nc,
                        c.max_items, c.items, c.meta, st);

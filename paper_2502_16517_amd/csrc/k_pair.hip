@@ -33,6 +33,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// head[q * kQStride] counts the items taken from queue q (one cache line per head).
 __device__ int next_item(int32_t* head, int n_items, int xcd, int& qoff)
 {
     while (qoff < kNumXcd) {
@@ -40,7 +41,7 @@ __device__ int next_item(int32_t* head, int n_items, int xcd, int& qoff)
         int lo = (int)(((int64_t)n_items * q) / kNumXcd);
         int hi = (int)(((int64_t)n_items * (q + 1)) / kNumXcd);
         if (lo < hi) {
-            int k = atomicAdd(&head[q], 1);
+            int k = atomicAdd(&head[q * kQStride], 1);
             if (lo + k < hi) return lo + k;
         }
         ++qoff;
@@ -48,16 +49,15 @@ __device__ int next_item(int32_t* head, int n_items, int xcd, int& qoff)
     return -1;
 }
 
-// Called by every lane 0 once its wave is done with the queue.
-__device__ void queue_exit(int32_t* meta, int qhead, int qexit)
+// Lane 0 of every wave leaves its counters in its own slots (plain stores: no
+// two waves share a cache line's worth of atomics at the end of the launch).
+__device__ __forceinline__ void leave_part(int64_t* part, int64_t c0, int64_t c1, int64_t c2, int64_t c3)
 {
-    __threadfence();
-    int done = atomicAdd(&meta[qexit], 1);
-    if (done == (int)gridDim.x - 1) {
-        for (int q = 0; q < kNumXcd; ++q) atomicExch(&meta[qhead + q], 0);
-        atomicExch(&meta[qexit], 0);
-        __threadfence();
-    }
+    int64_t* p = part + (int64_t)blockIdx.x * kPartSlots;
+    p[0] = c0;
+    p[1] = c1;
+    p[2] = c2;
+    p[3] = c3;
 }
 
 __device__ __forceinline__ void neumaier(float& s, float& c, float x)
@@ -743,12 +743,19 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
             if (lists) {
                 if (!done) {
                     // entries sl, sl + tpi, ... of the list; float partial sums are
-                    // folded into the compensated ones every 16 entries
+                    // folded into the compensated ones every 16 entries.  The index two
+                    // entries ahead and the union entry one ahead are read while the
+                    // current one is evaluated.
                     R p0 = 0, p1 = 0, p2 = 0;
                     int k = 0;
+                    int u_nx = sl + tpi < len ? s_list[lbase + sl + tpi] : 0;
+                    int u = sl < len ? s_list[lbase + sl] : 0;
+                    P4<R> c_nx = big.u[u];
                     for (int e = sl; e < len; e += tpi) {
-                        const int u = s_list[lbase + e];
-                        const P4<R> c = big.u[u];
+                        const P4<R> c = c_nx;
+                        const int e2 = e + 2 * tpi;
+                        const int u_n2 = e2 < len ? s_list[lbase + e2] : 0;
+                        c_nx = big.u[u_nx];
                         const R dx = xi - c.x;
                         const R dy = yi - c.y;
                         const R dz = zi - c.z;
@@ -761,6 +768,8 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                             p0 = p1 = p2 = 0;
                             k = 0;
                         }
+                        u = u_nx;
+                        u_nx = u_n2;
                     }
                     fold(p0, p1, p2);
                 }
@@ -912,16 +921,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
     n_evals = wave_sum_u64(n_evals);
     maxit = wave_max_i(maxit);
     for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
-    if (lane == 0) {
-        if (n_final) {
-            atomicAdd(&a.state->pairs_density, n_final);
-            atomicAdd(&a.state->pairs_total, n_final);
-        }
-        if (n_evals) atomicAdd(&a.state->pair_evals_density, n_evals);
-        if (maxit) atomicMax(&a.state->max_iters, maxit);
-        if (flags) atomicOr(&a.state->flags, flags);
-        queue_exit(a.meta, a.qhead, a.qexit);
-    }
+    if (lane == 0) leave_part(a.part, (int64_t)n_final, (int64_t)n_evals, maxit, flags);
 }
 
 // ================================================================== force
@@ -1215,14 +1215,7 @@ __global__ __launch_bounds__(kWave) void k_force(PairArgs a)
 
     n_pairs = wave_sum_u64(n_pairs);
     for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
-    if (lane == 0) {
-        if (n_pairs) {
-            atomicAdd(&a.state->pairs_force, n_pairs);
-            atomicAdd(&a.state->pairs_total, n_pairs);
-        }
-        if (flags) atomicOr(&a.state->flags, flags);
-        queue_exit(a.meta, a.qhead, a.qexit);
-    }
+    if (lane == 0) leave_part(a.part, (int64_t)n_pairs, 0, 0, flags);
 }
 
 // ============================================ time step and conservation sums
@@ -1317,11 +1310,67 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(RedArgs r, int64_t
 
 }  // namespace
 
+// Folds the per-wave counters of the pair loop that ran just before on the same
+// stream into the state block and rearms its queue for the next launch.  One
+// workgroup; integer sums, maxima and ors do not depend on the order.
+constexpr int kFoldThreads = 256;
+
+__global__ __launch_bounds__(kFoldThreads) void k_pair_fold(int32_t* meta, int qhead, const int64_t* part,
+                                                             int nblocks, DevState* st, int density)
+{
+    __shared__ unsigned long long s0[kFoldThreads / kWave], s1[kFoldThreads / kWave];
+    __shared__ int s2[kFoldThreads / kWave];
+    __shared__ uint32_t s3[kFoldThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    unsigned long long c0 = 0, c1 = 0;
+    int c2 = 0;
+    uint32_t c3 = 0;
+    for (int b = t; b < nblocks; b += kFoldThreads) {
+        const int64_t* p = part + (int64_t)b * kPartSlots;
+        c0 += (unsigned long long)p[0];
+        c1 += (unsigned long long)p[1];
+        c2 = (int)p[2] > c2 ? (int)p[2] : c2;
+        c3 |= (uint32_t)p[3];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c0 += __shfl_xor(c0, off, kWave);
+        c1 += __shfl_xor(c1, off, kWave);
+        const int o2 = __shfl_xor(c2, off, kWave);
+        c2 = o2 > c2 ? o2 : c2;
+        c3 |= __shfl_xor(c3, off, kWave);
+    }
+    if (lane == 0) {
+        s0[w] = c0;
+        s1[w] = c1;
+        s2[w] = c2;
+        s3[w] = c3;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int k = 1; k < kFoldThreads / kWave; ++k) {
+            c0 += s0[k];
+            c1 += s1[k];
+            c2 = s2[k] > c2 ? s2[k] : c2;
+            c3 |= s3[k];
+        }
+        if (density) {
+            st->pairs_density += c0;
+            st->pair_evals_density += c1;
+            if (c2 > st->max_iters) st->max_iters = c2;
+        } else {
+            st->pairs_force += c0;
+        }
+        st->pairs_total += c0;
+        st->flags |= c3;
+    }
+    if (t < kNumXcd) meta[qhead + t * kQStride] = 0;
+}
+
 int pair_grid_blocks(int64_t max_items)
 {
     // persistent grid: enough single-wave workgroups to fill 256 CUs several
     // times over, a multiple of the 8 XCDs
-    int64_t b = 256 * 20;
+    int64_t b = kMaxPairBlocks;
     if (max_items < b) b = (max_items + kNumXcd - 1) / kNumXcd * kNumXcd;
     if (b < kNumXcd) b = kNumXcd;
     return (int)b;
@@ -1352,12 +1401,20 @@ int pair_grid_blocks(int64_t max_items)
 hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
 {
     SPHV_DISPATCH(k_density, a, direct, fp32, masked, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
+                       a.nblocks, a.state, 1);
     return hipGetLastError();
 }
 
 hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
 {
     SPHV_DISPATCH(k_force, a, direct, fp32, masked, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
+                       a.nblocks, a.state, 0);
     return hipGetLastError();
 }
 
