@@ -23,6 +23,7 @@
 //    FP32: positions relative to the local cell's corner, pair arithmetic in
 //    float, per-chunk float partial sums folded into Neumaier-compensated
 //    float accumulators; Newton step and convergence test in double.
+#include <atomic>
 #include <type_traits>
 
 #include "k_common.h"
@@ -41,8 +42,13 @@ __device__ int next_item(int32_t* head, int n_items, int xcd, int& qoff)
         int lo = (int)(((int64_t)n_items * q) / kNumXcd);
         int hi = (int)(((int64_t)n_items * (q + 1)) / kNumXcd);
         if (lo < hi) {
-            int k = atomicAdd(&head[q * kQStride], 1);
-            if (lo + k < hi) return lo + k;
+            int32_t* hp = &head[q * kQStride];
+            // heads only grow: a queue read as drained is drained, and reading
+            // is cheaper than taking (the takes of one head serialise)
+            if (lo + __hip_atomic_load(hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
+                const int k = atomicAdd(hp, 1);
+                if (lo + k < hi) return lo + k;
+            }
         }
         ++qoff;
     }
@@ -453,7 +459,7 @@ __device__ __forceinline__ int wave_max_i(int v)
 // within twice the cell cap that its first pass cached.
 // The walk that builds the lists also writes those cap hits for the force loop.
 
-constexpr int kUMax = 256;     // union entries per work item (list entries are bytes)
+constexpr int kUMax = 320;     // union entries per work item
 constexpr int kPool = 2304;    // list entries per work item, split evenly over its particles
 constexpr double kListGrow = 1.0 + 1.0 / 16.0;
 
@@ -520,8 +526,8 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
     __shared__ DensStage<R> st;
     __shared__ SpanLds spans;
     __shared__ DensBig<R> big;
-    __shared__ uint8_t s_list[kPool];
-    __shared__ uint8_t s_uidx[kWave];
+    __shared__ uint16_t s_list[kPool];
+    __shared__ uint16_t s_uidx[kWave];
     __shared__ uint8_t s_flag[kWave];
     __shared__ int s_self[kWave];
     __shared__ int s_item;
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 nU += __popcll(bal);
                 if (f && u < kUMax) {
                     big.u[u] = P4<R>{sx[lane], sy[lane], sz[lane], sm[lane]};
-                    s_uidx[lane] = (uint8_t)u;
+                    s_uidx[lane] = (uint16_t)u;
                 }
                 // append this lane's hits to its particle's list, lanes in order
                 const int hl_n = __popcll(hits);
@@ -687,7 +693,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                     for (uint64_t m = hits; m; m &= m - 1) {
                         const int t = sl + __builtin_ctzll(m) * tpi;
                         const int u2 = s_uidx[t];
-                        s_list[lbase + k] = (uint8_t)u2;
+                        s_list[lbase + k] = (uint16_t)u2;
                         ++k;
                         if (sj[t] == pi) s_self[il] = u2;
                     }
@@ -927,7 +933,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
 // ================================================================== force
 
 template <bool DIRECT, bool FP32, bool MASKED>
-__global__ __launch_bounds__(kWave) void k_force(PairArgs a)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_force(PairArgs a)
 {
     using R = typename std::conditional<FP32, float, double>::type;
     // staged j data
@@ -1368,54 +1374,82 @@ __global__ __launch_bounds__(kFoldThreads) void k_pair_fold(int32_t* meta, int q
 
 int pair_grid_blocks(int64_t max_items)
 {
-    // persistent grid: enough single-wave workgroups to fill 256 CUs several
-    // times over, a multiple of the 8 XCDs
+    // persistent grid: at most enough single-wave workgroups to fill 256 CUs
+    // several times over, a multiple of the 8 XCDs
     int64_t b = kMaxPairBlocks;
     if (max_items < b) b = (max_items + kNumXcd - 1) / kNumXcd * kNumXcd;
     if (b < kNumXcd) b = kNumXcd;
     return (int)b;
 }
 
-#define SPHV_DISPATCH(KERNEL, a, direct, fp32, masked, s)                                                   \
-    do {                                                                                                   \
-        dim3 grid((unsigned)(a).nblocks), block(kWave);                                                    \
-        if (direct) {                                                                                      \
-            if (fp32) {                                                                                    \
-                if (masked) hipLaunchKernelGGL((KERNEL<true, true, true>), grid, block, 0, s, a);          \
-                else hipLaunchKernelGGL((KERNEL<true, true, false>), grid, block, 0, s, a);                \
-            } else {                                                                                       \
-                if (masked) hipLaunchKernelGGL((KERNEL<true, false, true>), grid, block, 0, s, a);         \
-                else hipLaunchKernelGGL((KERNEL<true, false, false>), grid, block, 0, s, a);               \
-            }                                                                                              \
-        } else {                                                                                           \
-            if (fp32) {                                                                                    \
-                if (masked) hipLaunchKernelGGL((KERNEL<false, true, true>), grid, block, 0, s, a);         \
-                else hipLaunchKernelGGL((KERNEL<false, true, false>), grid, block, 0, s, a);               \
-            } else {                                                                                       \
-                if (masked) hipLaunchKernelGGL((KERNEL<false, false, true>), grid, block, 0, s, a);        \
-                else hipLaunchKernelGGL((KERNEL<false, false, false>), grid, block, 0, s, a);              \
-            }                                                                                              \
-        }                                                                                                  \
+// Workgroups of a pair kernel that the device holds at once (its occupancy
+// times the compute units), a multiple of the 8 XCDs; queried once per kernel.
+template <class K>
+int resident_blocks(K kernel, std::atomic<int>& cache)
+{
+    int v = cache.load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus < 1)
+        cus = 256;
+    v = per_cu * cus / kNumXcd * kNumXcd;
+    if (v < kNumXcd) v = kNumXcd;
+    cache.store(v, std::memory_order_relaxed);
+    return v;
+}
+
+// Launches one instance with no more workgroups than the device holds at once
+// (a persistent grid gains nothing from waves that start after the queue has
+// drained), then the fold of its counters.
+template <class K>
+hipError_t launch_pair(K kernel, std::atomic<int>& cache, const PairArgs& a0, int density, hipStream_t s)
+{
+    PairArgs a = a0;
+    const int res = resident_blocks(kernel, cache);
+    if (a.nblocks > res) a.nblocks = res;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
+                       a.nblocks, a.state, density);
+    return hipGetLastError();
+}
+
+#define SPHV_PAIR_CASE(KERNEL, D, F, M, DENS)                                     \
+    do {                                                                          \
+        static std::atomic<int> cache{0};                                         \
+        return launch_pair(KERNEL<D, F, M>, cache, a, DENS, s);                    \
+    } while (0)
+
+#define SPHV_PAIR_DISPATCH(KERNEL, DENS)                                          \
+    do {                                                                          \
+        if (direct) {                                                             \
+            if (fp32) {                                                           \
+                if (masked) SPHV_PAIR_CASE(KERNEL, true, true, true, DENS);       \
+                SPHV_PAIR_CASE(KERNEL, true, true, false, DENS);                  \
+            }                                                                     \
+            if (masked) SPHV_PAIR_CASE(KERNEL, true, false, true, DENS);          \
+            SPHV_PAIR_CASE(KERNEL, true, false, false, DENS);                     \
+        }                                                                         \
+        if (fp32) {                                                               \
+            if (masked) SPHV_PAIR_CASE(KERNEL, false, true, true, DENS);          \
+            SPHV_PAIR_CASE(KERNEL, false, true, false, DENS);                     \
+        }                                                                         \
+        if (masked) SPHV_PAIR_CASE(KERNEL, false, false, true, DENS);             \
+        SPHV_PAIR_CASE(KERNEL, false, false, false, DENS);                        \
     } while (0)
 
 hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
 {
-    SPHV_DISPATCH(k_density, a, direct, fp32, masked, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
-                       a.nblocks, a.state, 1);
-    return hipGetLastError();
+    SPHV_PAIR_DISPATCH(k_density, 1);
 }
 
 hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
 {
-    SPHV_DISPATCH(k_force, a, direct, fp32, masked, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
-                       a.nblocks, a.state, 0);
-    return hipGetLastError();
+    SPHV_PAIR_DISPATCH(k_force, 0);
 }
 
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5, const Access& outacc,
