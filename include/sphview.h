@@ -185,15 +185,17 @@ int32_t sphv_write_state(void* state_dev, const sphv_state* in, void* stream);
  *   cell_start[c] .. cell_start[c+1] = the sorted positions of cell c.
  * A cell's reach R (cells per axis) covers 2 h headroom of its largest h; the
  * density loop of a particle in cell c visits the (2R+1)^3 cells around c and
- * its h is capped at R * min(cell) / 2; the force loop widens R to cover
- * neighbours' supports.  Work items are (cell, first sorted position, count<=64). */
+ * its h is capped at R * min(cell) / 2.  The force loop (sphv_sph_force) sets
+ * its own window from the converged h: R_f(c) is the largest of ceil(2 h_max(c)
+ * / min cell) and the Chebyshev distance of every cell whose own such reach
+ * covers c.  Work items are (cell, first sorted position, count<=64). */
 typedef struct sphv_cells sphv_cells;
 
 typedef struct {
     const int32_t* perm;        /* [n]          sorted position -> record index   */
     const int32_t* cell_start;  /* [n_cells+1]                                     */
     const int32_t* key;         /* [n]          key of record i (unsorted order)   */
-    const int32_t* reach;       /* [2*n_cells]  density reach, then force reach    */
+    const int32_t* reach;       /* [2*n_cells]  density reach, then the force window (set by sph_force) */
     int64_t n;
     int64_t n_cells;
     int64_t max_items;

@@ -251,8 +251,9 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
     c->counts = (int32_t*)take(4 * (uint64_t)nc);
     c->cursor = (int32_t*)take(4 * (uint64_t)nc);
     c->hmax_bits = (uint32_t*)take(4 * (uint64_t)nc);
-    c->reach_d = (int32_t*)take(4 * (uint64_t)nc * 2);
+    c->reach_d = (int32_t*)take(4 * (uint64_t)nc * 3);
     c->reach_f = c->reach_d ? c->reach_d + nc : nullptr;
+    c->reach_s = c->reach_d ? c->reach_d + 2 * nc : nullptr;
     c->tmp_a = (int32_t*)take(4 * (uint64_t)nc);
     c->tmp_b = (int32_t*)take(4 * (uint64_t)nc);
     c->item_start = (int32_t*)take(4 * (uint64_t)(nc + 1));
@@ -700,9 +701,15 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
         return SPHV_E_INVALID_ARG;
     if (v->n == 0) return SPHV_OK;
     a.reach = c->dev.reach_f;
+    a.reach_s = c->dev.reach_s;
     a.qhead = META_QHEAD_F;
     hipStream_t st = (hipStream_t)stream;
     bool direct = v->layout.kind == SPHV_LAYOUT_DIRECT;
+    // windows from the converged h: members a view only reads are never
+    // modified while it is open, so the records hold them
+    const FieldRef hrec = ref_rec(v->aos, v->plan[v->role_field[SPHV_H]].f);
+    hipError_t e = launch_force_reach(c->dev, hrec, v->desc.stride, a.g, (DevState*)state, st);
+    if (e != hipSuccess) return SPHV_E_HIP;
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, st));
 }
 

@@ -73,8 +73,9 @@ struct CellsDev {
     int32_t* counts;       // [nc]
     int32_t* cursor;       // [nc]
     uint32_t* hmax_bits;   // [nc] float bits of 2 h headroom max
-    int32_t* reach_d;      // [nc]
-    int32_t* reach_f;      // [nc]
+    int32_t* reach_d;      // [nc] density reach (cells_build, from h before the density loop)
+    int32_t* reach_f;      // [nc] force window radius (sph_force, from the converged h)
+    int32_t* reach_s;      // [nc] upper bound of the neighbours' own force reach (box maximum)
     int32_t* tmp_a;        // [nc] scratch for the reach filter / item counts
     int32_t* tmp_b;        // [nc]
     int32_t* item_start;   // [nc + 1]
@@ -82,7 +83,7 @@ struct CellsDev {
     uint64_t* item_masks;  // [max_items][kMaskChunks][64] candidate hit masks of the density loop
     int64_t* pair_part;    // [kMaxPairBlocks][kPartSlots] per-wave counters of the last pair loop
     int32_t* scan_part;    // [scan blocks + 1]
-    int32_t* meta;         // [META_SIZE]: item count, R_global, mask tag, queue heads
+    int32_t* meta;         // [META_SIZE]: item count, mask tag, force R_global, queue heads
     int64_t n;
     int64_t nc;
     int64_t max_items;
@@ -91,8 +92,8 @@ struct CellsDev {
 // meta[] slots
 enum {
     META_NITEMS = 0,
-    META_RGLOBAL = 1,
     META_MASKS = 2,                          // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
+    META_RGLOBAL_F = 3,                      // largest own force reach
     META_QHEAD_D = 64,                       // 8 per-XCD heads of the density queue, kQStride apart
     META_QHEAD_F = 64 + kNumXcd * kQStride,  // the same for the force queue
     META_SIZE = 64 + 2 * kNumXcd * kQStride
@@ -108,6 +109,7 @@ struct PairArgs {
     const int32_t* reach;      // density or force reach
     const int32_t* key_sorted; // cell of sorted position p
     const int32_t* reach_d;    // density reach (the force loop compares it with its own)
+    const int32_t* reach_s;    // force: bound of the own force reach of the cells around
     uint64_t* item_masks;      // cached candidate masks (see CellsDev)
     int32_t* meta;             // queue counters
     int64_t* part;             // per-wave counters, folded by the launch that follows
@@ -131,6 +133,8 @@ hipError_t launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_state_init(DevState* st, int full, hipStream_t s);
 hipError_t launch_cells_build(const CellsDev& c, const FieldRef* xyzh, const Access& rec,
                               const Geom& g, DevState* st, hipStream_t s);
+hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Geom& g, DevState* st,
+                              hipStream_t s);
 hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
                          const Access& dst_acc, const int32_t* cell_key, const Geom& g, int64_t n,
                          hipStream_t s);

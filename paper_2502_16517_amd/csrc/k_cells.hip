@@ -260,34 +260,13 @@ __global__ void k_items(const int32_t* cell_start, const int32_t* item_start, in
     }
 }
 
-// R_global = max of the cells' reach: a block maximum each, one atomic per block
-constexpr int kMaxThreads = 1024;
-
-__global__ __launch_bounds__(kMaxThreads) void k_reach_max(const int32_t* reach, int64_t nc, int32_t* meta)
-{
-    __shared__ int s[kMaxThreads / kWave];
-    int m = 0;
-    for (int64_t c = (int64_t)blockIdx.x * kMaxThreads + threadIdx.x; c < nc; c += (int64_t)gridDim.x * kMaxThreads)
-        m = reach[c] > m ? reach[c] : m;
-    for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(m, off, kWave);
-        m = o > m ? o : m;
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < kMaxThreads / kWave; ++k) m = s[k] > m ? s[k] : m;
-        if (m > 0) atomicMax(&meta[META_RGLOBAL], m);
-    }
-}
-
 // box max of reach along one axis over +-R_global cells (wrapped or clipped)
-__global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, const int32_t* meta, int64_t nc,
-                             DevState* st)
+__global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, const int32_t* meta, int rslot,
+                             int64_t nc, DevState* st)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
-    int R = meta[META_RGLOBAL];
+    int R = meta[rslot];
     int n = g.n[axis];
     if (g.periodic[axis] && 2 * R + 1 > n) {
         if (c == 0) set_flag(st, SPHV_F_GRID_TOO_SMALL);
@@ -309,6 +288,103 @@ __global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, 
         m = v > m ? v : m;
     }
     out[c] = m;
+}
+
+// Own force reach of every cell from its largest converged h: R = ceil(2 h / min
+// cell) (0 for an empty cell), widened by 1e-12 so rounding never shrinks it;
+// one wave per cell, a block maximum each into meta[rslot].
+constexpr int kOwnWaves = 4;
+
+__global__ __launch_bounds__(kOwnWaves * kWave) void k_force_own(const int32_t* cell_start, const int32_t* perm,
+                                                                 FieldRef h, uint64_t stride, double cmin,
+                                                                 int32_t* own, int32_t* meta, int rslot, int64_t nc)
+{
+    __shared__ int s[kOwnWaves];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int64_t c = (int64_t)blockIdx.x * kOwnWaves + w;
+    int R = 0;
+    if (c < nc) {
+        const int b = cell_start[c], e = cell_start[c + 1];
+        double hm = 0.0;
+        for (int p = b + lane; p < e; p += kWave) {
+            const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
+            hm = v > hm ? v : hm;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(hm, off, kWave);
+            hm = o > hm ? o : hm;
+        }
+        if (e > b) {
+            R = (int)ceil(2.0 * hm * (1.0 + 1e-12) / cmin);
+            if (R < 1) R = 1;
+        }
+        if (lane == 0) own[c] = R;
+    }
+    if (lane == 0) s[w] = R;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = s[0];
+        for (int k = 1; k < kOwnWaves; ++k) m = s[k] > m ? s[k] : m;
+        if (m > 0) atomicMax(&meta[rslot], m);
+    }
+}
+
+// Exact force window: cell A must see every cell B whose own reach covers it,
+// R_f(A) = max(R(A), max{ d(A,B) : d(A,B) <= R(B) }) with d the Chebyshev
+// distance in cells.  sep, the box maximum of R over +-R_global, bounds it from
+// above and stands in when R_global is large or a periodic axis is short;
+// otherwise shells are scanned from the outermost (at most the bound) inward.
+constexpr int kExactReach = 4;
+
+__global__ void k_reach_exact(const int32_t* own_r, const int32_t* sep, int32_t* out, Geom g, const int32_t* meta,
+                              int rslot, int64_t nc)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int R = meta[rslot];
+    bool exact = R <= kExactReach;
+    for (int d = 0; d < 3; ++d)
+        if (g.periodic[d] && 2 * R + 1 > g.n[d]) exact = false;
+    if (!exact) {
+        out[c] = sep[c];
+        return;
+    }
+    int k[3];
+    cell_coords((int)c, g, k[0], k[1], k[2]);
+    const int own = own_r[c];
+    int best = own;
+    const int top = sep[c] < R ? sep[c] : R;
+    for (int d = top; d > own && best == own; --d) {
+        for (int dz = -d; dz <= d && best == own; ++dz) {
+            int z = k[2] + dz;
+            if (z < 0 || z >= g.n[2]) {
+                if (!g.periodic[2]) continue;
+                z = z < 0 ? z + g.n[2] : z - g.n[2];
+            }
+            for (int dy = -d; dy <= d && best == own; ++dy) {
+                int y = k[1] + dy;
+                if (y < 0 || y >= g.n[1]) {
+                    if (!g.periodic[1]) continue;
+                    y = y < 0 ? y + g.n[1] : y - g.n[1];
+                }
+                const bool face = dz == -d || dz == d || dy == -d || dy == d;
+                const int step = face ? 1 : 2 * d;
+                for (int dx = -d; dx <= d; dx += step) {
+                    int x = k[0] + dx;
+                    if (x < 0 || x >= g.n[0]) {
+                        if (!g.periodic[0]) continue;
+                        x = x < 0 ? x + g.n[0] : x - g.n[0];
+                    }
+                    if (own_r[cell_key(x, y, z, g)] >= d) {
+                        best = d;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    out[c] = best;
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
@@ -350,21 +426,31 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
                        c.key_sorted, c.hmax_bits, c.reach_d, c.tmp_a, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    {
-        const unsigned mb = (unsigned)std::min<int64_t>(std::max<int64_t>((c.nc + kMaxThreads - 1) / kMaxThreads, 1), 64);
-        hipLaunchKernelGGL(k_reach_max, dim3(mb), dim3(kMaxThreads), 0, s, c.reach_d, c.nc, c.meta);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.nc,
                        c.max_items, c.items, c.meta, st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.reach_d, c.tmp_b, g, 0, c.meta,
-                       c.nc, st);
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_b, c.tmp_a, g, 1, c.meta,
-                       c.nc, st);
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.reach_f, g, 2, c.meta,
-                       c.nc, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Geom& g, DevState* st,
+                              hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_fill_u32(c.meta + META_RGLOBAL_F, 0u, 1, s)) != hipSuccess) return e;
+    const unsigned nb = (unsigned)std::max<int64_t>((c.nc + kOwnWaves - 1) / kOwnWaves, 1);
+    hipLaunchKernelGGL(k_force_own, dim3(nb), dim3(kOwnWaves * kWave), 0, s, c.cell_start, c.perm, h, stride, g.cmin,
+                       c.tmp_a, c.meta, (int)META_RGLOBAL_F, c.nc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // separable box maximum over +-R_global (tmp_a -> tmp_b -> reach_f -> reach_s), then the exact window
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.tmp_b, g, 0, c.meta,
+                       (int)META_RGLOBAL_F, c.nc, st);
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_b, c.reach_f, g, 1, c.meta,
+                       (int)META_RGLOBAL_F, c.nc, st);
+    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.reach_f, c.reach_s, g, 2, c.meta,
+                       (int)META_RGLOBAL_F, c.nc, st);
+    hipLaunchKernelGGL(k_reach_exact, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.reach_s, c.reach_f, g, c.meta,
+                       (int)META_RGLOBAL_F, c.nc);
     return hipGetLastError();
 }
 

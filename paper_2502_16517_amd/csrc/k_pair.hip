@@ -977,9 +977,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         cell_coords(cell, a.g, kx, ky, kz);
         int r[3];
         axis_reach(a, a.reach[cell], r);
-        // same window as the density loop and the same lanes per particle: its
-        // cached candidate masks apply
-        const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && a.reach[cell] == a.reach_d[cell];
+        // the density loop cached the candidates within twice its cell cap for
+        // this window; they hold every force pair when the windows agree and no
+        // cell around has a larger own force reach (no neighbour's support
+        // reaches further than the cap)
+        const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && a.reach[cell] == a.reach_d[cell] &&
+                           a.reach_s[cell] <= a.reach_d[cell];
         int n_spans = 0, W = 0;
         const bool use_spans = build_spans(a, kx, ky, kz, r, lane, spans, n_spans, W);
 

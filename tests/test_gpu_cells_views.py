@@ -46,6 +46,59 @@ def test_cells_build_exact(orc, name):
     assert state.flags & ~sv.F_OUT_OF_BOX == 0
 
 
+def _window_model(w, own):
+    """Exact force window: R_f(A) = max(R(A), max{d : a cell B at Chebyshev
+    distance d has own reach R(B) >= d})."""
+    g = tuple(int(v) for v in w.grid)
+    R = own.reshape(g[2], g[1], g[0])
+    Rg = int(R.max())
+    out = R.copy()
+    for dz in range(-Rg, Rg + 1):
+        for dy in range(-Rg, Rg + 1):
+            for dx in range(-Rg, Rg + 1):
+                d = max(abs(dx), abs(dy), abs(dz))
+                if d == 0:
+                    continue
+                sh = np.roll(R, shift=(-dz, -dy, -dx), axis=(0, 1, 2))   # sh[A] = R[A + offset]
+                valid = np.ones_like(R, dtype=bool)
+                for ax, off, per in ((2, dx, w.periodic[0]), (1, dy, w.periodic[1]), (0, dz, w.periodic[2])):
+                    if not per:
+                        idx = np.arange(R.shape[ax]) + off
+                        shape = [1, 1, 1]
+                        shape[ax] = -1
+                        valid &= ((idx >= 0) & (idx < R.shape[ax])).reshape(shape)
+                out = np.maximum(out, np.where(valid & (sh >= d), d, 0))
+    return out.ravel(), Rg
+
+
+@pytest.mark.parametrize("steps", [1, 6])
+def test_force_window_is_exact(orc, steps):
+    """The force loop's window of every cell holds each cell whose own force
+    reach (from the converged h, no headroom) covers it, and for R_global <= 4
+    on long periodic axes nothing more."""
+    w = inputs.two_state_tube(24, 31)
+    st = _stepper(w)
+    for _ in range(steps):
+        st.step()
+    perm, start, _, reach = st.cells_arrays()
+    rec = st.records()
+    p = st.p
+    st.close()
+    nc = w.grid[0] * w.grid[1] * w.grid[2]
+    rf = reach[nc:2 * nc]
+    h = rec[perm, S["h"]]
+    cmin = min(p.cell[0], p.cell[1], p.cell[2])
+    own = np.zeros(nc, dtype=np.int64)
+    for c in range(nc):
+        if start[c + 1] > start[c]:
+            hm = h[start[c]:start[c + 1]].max()
+            own[c] = max(1, int(np.ceil(2.0 * hm * (1.0 + 1e-12) / cmin)))
+    exact, Rg = _window_model(w, own)
+    assert (rf >= exact).all()
+    if Rg <= 4 and all(2 * Rg + 1 <= n for n in w.grid):
+        assert np.array_equal(rf, exact)
+
+
 def test_cells_flags_nonfinite(orc):
     w = inputs.config1()
     w.rec[5, S["x"]] = np.nan
