@@ -72,7 +72,7 @@ struct CellsDev {
     int32_t* cell_start;   // [nc + 1]
     int32_t* counts;       // [nc]
     int32_t* cursor;       // [nc]
-    uint32_t* hmax_bits;   // [nc] float bits of 2 h headroom max
+    uint32_t* hmax_bits;   // [nc] float bits of the largest 2 h (times the headroom for the density reach)
     int32_t* reach_d;      // [nc] density reach (cells_build, from h before the density loop)
     int32_t* reach_f;      // [nc] force window radius (sph_force, from the converged h)
     int32_t* reach_s;      // [nc] upper bound of the neighbours' own force reach (box maximum)

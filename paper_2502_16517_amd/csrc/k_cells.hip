@@ -182,7 +182,7 @@ constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
 __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_start, const int32_t* perm_tmp,
                                                           int32_t* perm, int32_t* key_sorted,
                                                           const uint32_t* hmax_bits, int32_t* reach_d,
-                                                          int32_t* item_cnt, Geom g, int64_t nc)
+                                                          Geom g, int64_t nc)
 {
     __shared__ int lds[kSortWaves][kSortLds];
     const int lane = threadIdx.x & (kWave - 1);
@@ -234,29 +234,121 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
                 if (R < 1) R = 1;
             }
             reach_d[c] = R;
-            item_cnt[c] = (cnt + kWave - 1) / kWave;
         }
     }
 }
 
-__global__ void k_items(const int32_t* cell_start, const int32_t* item_start, int64_t nc, int64_t max_items,
-                        int4* items, int32_t* meta, DevState* st)
+// Work items, one wave per row of cells along x.  A cell with more than
+// kSparse particles is its own item (split at 64).  Runs of consecutive sparse
+// cells of one row (empty cells included) whose density reach is at most
+// kGroupReach and equal, and whose neighbourhood of +-kGroupReach cells in y,
+// z and beyond the run in x holds only sparse cells, form one item of at most
+// kGroupLen cells and kGroupMax particles; its window is the run widened by
+// the reach, and on a periodic x axis it must not wrap onto itself (2 R + cells
+// <= n_x).  Items are (first cell, first sorted position, particles, cells).
+// Pass 1 counts the items of every row, pass 2 writes them at the row's offset.
+constexpr int kSparse = 8;
+constexpr int kGroupMax = 24;
+constexpr int kGroupLen = 6;
+constexpr int kGroupReach = 2;
+constexpr int kRowMax = 1024;   // rows up to this length are staged in LDS and grouped
+
+template <bool WRITE>
+__global__ __launch_bounds__(kWave) void k_row_items(const int32_t* cell_start, const int32_t* reach_d, Geom g,
+                                                     int64_t nrows, int32_t* row_cnt, const int32_t* row_start,
+                                                     int64_t max_items, int4* items, int32_t* meta, DevState* st)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c == 0) {
-        int total = item_start[nc];
+    __shared__ int scnt[kRowMax], srch[kRowMax], scol[kRowMax];
+    const int lane = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int64_t base = row * nx;
+    const int ky = (int)(row % ny), kz = (int)(row / ny);
+    const bool staged = nx <= kRowMax;
+    if (staged) {
+        for (int x = lane; x < nx; x += kWave) {
+            scnt[x] = cell_start[base + x + 1] - cell_start[base + x];
+            srch[x] = reach_d[base + x];
+            // densest cell of column x over the rows within +-kGroupReach in y and z
+            int m = 0;
+            for (int dz = -kGroupReach; dz <= kGroupReach; ++dz) {
+                int z = kz + dz;
+                if (z < 0 || z >= nz) {
+                    if (!g.periodic[2]) continue;
+                    z = z < 0 ? z + nz : z - nz;
+                }
+                for (int dy = -kGroupReach; dy <= kGroupReach; ++dy) {
+                    int y = ky + dy;
+                    if (y < 0 || y >= ny) {
+                        if (!g.periodic[1]) continue;
+                        y = y < 0 ? y + ny : y - ny;
+                    }
+                    const int64_t c = ((int64_t)z * ny + y) * nx + x;
+                    const int v = cell_start[c + 1] - cell_start[c];
+                    m = v > m ? v : m;
+                }
+            }
+            scol[x] = m;
+        }
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    // the densest column of the run x0..x1 widened by kGroupReach along x
+    auto sparse_around = [&](int x0, int x1) {
+        for (int x = x0 - kGroupReach; x <= x1 + kGroupReach; ++x) {
+            int xx = x;
+            if (xx < 0 || xx >= nx) {
+                if (!g.periodic[0]) continue;
+                xx = xx < 0 ? xx + nx : xx - nx;
+            }
+            if (scol[xx] > kSparse) return false;
+        }
+        return true;
+    };
+    int64_t o = WRITE ? row_start[row] : 0;
+    int nitems = 0;
+    int x = 0;
+    while (x < nx) {
+        const int c0 = staged ? scnt[x] : cell_start[base + x + 1] - cell_start[base + x];
+        const bool groupable = staged && c0 <= kSparse && (c0 == 0 || srch[x] <= kGroupReach) &&
+                               (!g.periodic[0] || 2 * kGroupReach + 1 <= nx) && sparse_around(x, x);
+        if (!groupable) {
+            const int first = cell_start[base + x];
+            for (int f = 0; f < c0; f += kWave) {
+                if (WRITE && o < max_items) items[o] = make_int4((int)(base + x), first + f, min(kWave, c0 - f), 1);
+                ++o;
+                ++nitems;
+            }
+            ++x;
+            continue;
+        }
+        int R = c0 > 0 ? srch[x] : 0, tot = c0, gx = 1;
+        while (x + gx < nx && gx < kGroupLen) {
+            const int c2 = scnt[x + gx];
+            if (c2 > kSparse || tot + c2 > kGroupMax) break;
+            const int r2 = c2 > 0 ? srch[x + gx] : 0;
+            if (r2 > kGroupReach || (c2 > 0 && R > 0 && r2 != R)) break;
+            if (g.periodic[0] && 2 * kGroupReach + gx + 1 > nx) break;
+            if (!sparse_around(x, x + gx)) break;
+            tot += c2;
+            R = R > r2 ? R : r2;
+            ++gx;
+        }
+        if (tot > 0) {
+            if (WRITE && o < max_items) items[o] = make_int4((int)(base + x), cell_start[base + x], tot, gx);
+            ++o;
+            ++nitems;
+        }
+        x += gx;
+    }
+    if (!WRITE) row_cnt[row] = nitems;
+    if (WRITE && row == 0) {
+        int total = row_start[nrows];
         if (total > max_items) {
             set_flag(st, SPHV_F_QUEUE_OVERFLOW);
             total = (int)max_items;
         }
         meta[META_NITEMS] = total;
-    }
-    if (c >= nc) return;
-    int b = cell_start[c], e = cell_start[c + 1];
-    int o = item_start[c];
-    for (int f = b; f < e; f += kWave) {
-        if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 0);
-        ++o;
     }
 }
 
@@ -291,41 +383,44 @@ __global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, 
 }
 
 // Own force reach of every cell from its largest converged h: R = ceil(2 h / min
-// cell) (0 for an empty cell), widened by 1e-12 so rounding never shrinks it;
-// one wave per cell, a block maximum each into meta[rslot].
-constexpr int kOwnWaves = 4;
-
-__global__ __launch_bounds__(kOwnWaves * kWave) void k_force_own(const int32_t* cell_start, const int32_t* perm,
-                                                                 FieldRef h, uint64_t stride, double cmin,
-                                                                 int32_t* own, int32_t* meta, int rslot, int64_t nc)
+// cell) (0 for an empty cell), widened by 1e-12 so rounding never shrinks it.
+// k_force_hbits folds 2 h of every particle into its cell (float bits rounded
+// up, as k_bin does); k_force_own turns them into R and a block maximum of R
+// into meta[rslot] (one atomic per block of 1024 cells).
+__global__ void k_force_hbits(const int32_t* perm, const int32_t* key_sorted, FieldRef h, uint64_t stride,
+                              int64_t n, uint32_t* hbits)
 {
-    __shared__ int s[kOwnWaves];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    const int64_t c = (int64_t)blockIdx.x * kOwnWaves + w;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
+    atomicMax(&hbits[key_sorted[p]], __float_as_uint(__double2float_ru(2.0 * v)));
+}
+
+constexpr int kOwnThreads = 1024;
+
+__global__ __launch_bounds__(kOwnThreads) void k_force_own(const int32_t* cell_start, const uint32_t* hbits,
+                                                          double cmin, int32_t* own, int32_t* meta, int rslot,
+                                                          int64_t nc)
+{
+    __shared__ int s[kOwnThreads / kWave];
+    const int64_t c = (int64_t)blockIdx.x * kOwnThreads + threadIdx.x;
     int R = 0;
     if (c < nc) {
-        const int b = cell_start[c], e = cell_start[c + 1];
-        double hm = 0.0;
-        for (int p = b + lane; p < e; p += kWave) {
-            const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
-            hm = v > hm ? v : hm;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(hm, off, kWave);
-            hm = o > hm ? o : hm;
-        }
-        if (e > b) {
-            R = (int)ceil(2.0 * hm * (1.0 + 1e-12) / cmin);
+        if (cell_start[c + 1] > cell_start[c]) {
+            R = (int)ceil((double)__uint_as_float(hbits[c]) * (1.0 + 1e-12) / cmin);
             if (R < 1) R = 1;
         }
-        if (lane == 0) own[c] = R;
+        own[c] = R;
     }
-    if (lane == 0) s[w] = R;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(R, off, kWave);
+        R = o > R ? o : R;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = R;
     __syncthreads();
     if (threadIdx.x == 0) {
         int m = s[0];
-        for (int k = 1; k < kOwnWaves; ++k) m = s[k] > m ? s[k] : m;
+        for (int k = 1; k < kOwnThreads / kWave; ++k) m = s[k] > m ? s[k] : m;
         if (m > 0) atomicMax(&meta[rslot], m);
     }
 }
@@ -424,11 +519,14 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     }
     unsigned sb = (unsigned)std::min<int64_t>((c.nc + kSortWaves - 1) / kSortWaves, 8192);
     hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
-                       c.key_sorted, c.hmax_bits, c.reach_d, c.tmp_a, g, c.nc);
+                       c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.nc,
-                       c.max_items, c.items, c.meta, st);
+    const int64_t nrows = (int64_t)g.n[1] * g.n[2];
+    hipLaunchKernelGGL(k_row_items<false>, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, nrows,
+                       c.tmp_a, (const int32_t*)nullptr, c.max_items, c.items, c.meta, st);
+    if ((e = scan_excl(c.tmp_a, nrows, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_items<true>, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, nrows,
+                       c.tmp_a, (const int32_t*)c.item_start, c.max_items, c.items, c.meta, st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -438,9 +536,14 @@ hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t str
 {
     hipError_t e;
     if ((e = launch_fill_u32(c.meta + META_RGLOBAL_F, 0u, 1, s)) != hipSuccess) return e;
-    const unsigned nb = (unsigned)std::max<int64_t>((c.nc + kOwnWaves - 1) / kOwnWaves, 1);
-    hipLaunchKernelGGL(k_force_own, dim3(nb), dim3(kOwnWaves * kWave), 0, s, c.cell_start, c.perm, h, stride, g.cmin,
-                       c.tmp_a, c.meta, (int)META_RGLOBAL_F, c.nc);
+    if ((e = launch_fill_u32(c.hmax_bits, 0u, c.nc, s)) != hipSuccess) return e;
+    if (c.n > 0) {
+        hipLaunchKernelGGL(k_force_hbits, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h, stride, c.n,
+                           c.hmax_bits);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_bits,
+                       g.cmin, c.tmp_a, c.meta, (int)META_RGLOBAL_F, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // separable box maximum over +-R_global (tmp_a -> tmp_b -> reach_f -> reach_s), then the exact window
     hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.tmp_b, g, 0, c.meta,

@@ -135,28 +135,30 @@ template <class R> struct Tiny;
 template <> struct Tiny<double> { static constexpr double v = 1e-300; };
 template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
 
-// Per-axis reach of a cell, guarded against windows that wrap onto themselves.
-__device__ __forceinline__ void axis_reach(const PairArgs& a, int R, int r[3])
+// Per-axis reach of a work item spanning gx cells along x, guarded against
+// windows that wrap onto themselves.
+__device__ __forceinline__ void axis_reach(const PairArgs& a, int R, int gx, int r[3])
 {
     bool small = false;
     for (int d = 0; d < 3; ++d) {
+        const int span = d == 0 ? gx : 1;
         r[d] = R;
-        if (a.g.periodic[d] && 2 * R + 1 > a.g.n[d]) {
-            r[d] = (a.g.n[d] - 1) / 2;
+        if (a.g.periodic[d] && 2 * R + span > a.g.n[d]) {
+            r[d] = (a.g.n[d] - span) / 2;
             small = true;
         }
     }
     if (small && threadIdx.x == 0) set_flag(a.state, SPHV_F_GRID_TOO_SMALL);
 }
 
-// Walk the window of cell (kx,ky,kz): every contiguous span of candidates with
+// Walk the window of cells kx..kx+gx-1 of row (ky,kz): every contiguous span of candidates with
 // its periodic image (ix,iy,iz in {-1,0,1}), staged 64 at a time into LDS slot
 // 'lane'.  stage(j, ix, iy, iz) is called by the lane that owns the slot;
 // compute(count, chunk) runs between barriers once 64 candidates (or the rest)
 // are in; chunk numbers the batches 0, 1, ... in this fixed order.
 template <class Stage, class Compute>
-__device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], int lane,
-                                           Stage&& stage, Compute&& compute)
+__device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, int kz, int gx, const int r[3],
+                                           int lane, Stage&& stage, Compute&& compute)
 {
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
     int fill = 0;
@@ -176,7 +178,7 @@ __device__ __forceinline__ void for_window(const PairArgs& a, int kx, int ky, in
                 y2 -= iy * ny;
             }
             const int row = (z2 * ny + y2) * nx;
-            const int x0 = kx - r[0], x1 = kx + r[0];
+            const int x0 = kx - r[0], x1 = kx + gx - 1 + r[0];
             const bool per = a.g.periodic[0] != 0;
             // up to three spans: wrapped left part, main part, wrapped right part
             for (int sgi = 0; sgi < 3; ++sgi) {
@@ -273,10 +275,10 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total)
     return x - v;
 }
 
-// Fills L for the window of cell (kx, ky, kz) with per-axis reach r; returns
+// Fills L for the window of cells kx..kx+gx-1 of row (ky, kz) with per-axis reach r; returns
 // false (for every lane) when the window exceeds the table, leaving the
 // caller to walk it with for_window.
-__device__ bool build_spans(const PairArgs& a, int kx, int ky, int kz, const int r[3], int lane, SpanLds& L,
+__device__ bool build_spans(const PairArgs& a, int kx, int ky, int kz, int gx, const int r[3], int lane, SpanLds& L,
                             int& ns_out, int& W_out)
 {
     if (a.n >= (1ll << kSpanPosBits)) return false;
@@ -304,7 +306,7 @@ __device__ bool build_spans(const PairArgs& a, int kx, int ky, int kz, const int
             }
             if (ok) {
                 const int row = (z2 * ny + y2) * nx;
-                const int x0 = kx - r[0], x1 = kx + r[0];
+                const int x0 = kx - r[0], x1 = kx + gx - 1 + r[0];
                 const bool per = a.g.periodic[0] != 0;
                 vl = per && x0 < 0;
                 vr = per && x1 >= nx;
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
         if (item < 0) break;
 
         const int4 it = a.items[item];
-        const int cell = it.x, first = it.y, ni = it.z;
+        const int cell = it.x, first = it.y, ni = it.z, gx = it.w;
         int tpi = kWave / ni;
         if (a.tpi > 0 && a.tpi < tpi) tpi = a.tpi;
         const int il = lane / tpi, sl = lane - il * tpi;
@@ -563,8 +565,10 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
         const int pi = first + (act ? il : 0);
         int kx, ky, kz;
         cell_coords(cell, a.g, kx, ky, kz);
+        int Rg = 0;   // the item's reach: the largest of its cells (equal, empty cells aside)
+        for (int k = 0; k < gx; ++k) Rg = a.reach[cell + k] > Rg ? a.reach[cell + k] : Rg;
         int r[3];
-        axis_reach(a, a.reach[cell], r);
+        axis_reach(a, Rg, gx, r);
         double hcap = 0.5 * (double)r[0] * a.g.cell[0];
         hcap = fmin(hcap, 0.5 * (double)r[1] * a.g.cell[1]);
         hcap = fmin(hcap, 0.5 * (double)r[2] * a.g.cell[2]);
@@ -579,10 +583,14 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
         R xi, yi, zi;
         double mi;
         if constexpr (FP32) {
-            xi = ld_as_f32(a.f[SPHV_X], li, a.g, cell);
-            yi = ld_as_f32(a.f[SPHV_Y], li, a.g, cell);
-            zi = ld_as_f32(a.f[SPHV_Z], li, a.g, cell);
-            mi = (double)ld_as_f32(a.f[SPHV_M], li, a.g, cell);
+            // relative to the corner of the item's first cell, as the candidates are staged
+            const int own = a.key_sorted[pi];
+            int ox, oy, oz;
+            cell_coords(own, a.g, ox, oy, oz);
+            xi = ld_as_f32(a.f[SPHV_X], li, a.g, own) + __double2float_rn((double)(ox - kx) * a.g.cell[0]);
+            yi = ld_as_f32(a.f[SPHV_Y], li, a.g, own) + __double2float_rn((double)(oy - ky) * a.g.cell[1]);
+            zi = ld_as_f32(a.f[SPHV_Z], li, a.g, own) + __double2float_rn((double)(oz - kz) * a.g.cell[2]);
+            mi = (double)ld_as_f32(a.f[SPHV_M], li, a.g, own);
         } else {
             xi = ld_f64(a.f[SPHV_X], li);
             yi = ld_f64(a.f[SPHV_Y], li);
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
         const double hl = fmin(hcap, kListGrow * h0);
         const R Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
         int n_spans = 0, W = 0;
-        const bool use_spans = build_spans(a, kx, ky, kz, r, lane, spans, n_spans, W);
+        const bool use_spans = build_spans(a, kx, ky, kz, gx, r, lane, spans, n_spans, W);
 
         // staging of one candidate: fetch issues the loads (raw members), put
         // converts them and writes this lane's LDS slot
@@ -831,7 +839,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                     fold(p0, p1, p2);
                 };
                 if (use_spans) run_window(spans, W, lane, fetch, put, compute);
-                else for_window(a, kx, ky, kz, r, lane, stage, compute);
+                else for_window(a, kx, ky, kz, gx, r, lane, stage, compute);
             }
 
             if constexpr (FP32) {
@@ -967,7 +975,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         if (item < 0) break;
 
         const int4 it = a.items[item];
-        const int cell = it.x, first = it.y, ni = it.z;
+        const int cell = it.x, first = it.y, ni = it.z, gx = it.w;
         int tpi = kWave / ni;
         if (a.tpi > 0 && a.tpi < tpi) tpi = a.tpi;
         const int il = lane / tpi, sl = lane - il * tpi;
@@ -975,24 +983,35 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         const int pi = first + (act ? il : 0);
         int kx, ky, kz;
         cell_coords(cell, a.g, kx, ky, kz);
+        // the item's force window, density reach and neighbours' bound: the
+        // largest over its cells
+        int Rf = 0, Rd = 0, Rs = 0;
+        for (int k = 0; k < gx; ++k) {
+            Rf = a.reach[cell + k] > Rf ? a.reach[cell + k] : Rf;
+            Rd = a.reach_d[cell + k] > Rd ? a.reach_d[cell + k] : Rd;
+            Rs = a.reach_s[cell + k] > Rs ? a.reach_s[cell + k] : Rs;
+        }
         int r[3];
-        axis_reach(a, a.reach[cell], r);
+        axis_reach(a, Rf, gx, r);
         // the density loop cached the candidates within twice its cell cap for
         // this window; they hold every force pair when the windows agree and no
         // cell around has a larger own force reach (no neighbour's support
         // reaches further than the cap)
-        const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && a.reach[cell] == a.reach_d[cell] &&
-                           a.reach_s[cell] <= a.reach_d[cell];
+        const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && Rf == Rd && Rs <= Rd;
         int n_spans = 0, W = 0;
-        const bool use_spans = build_spans(a, kx, ky, kz, r, lane, spans, n_spans, W);
+        const bool use_spans = build_spans(a, kx, ky, kz, gx, r, lane, spans, n_spans, W);
 
         // local particle i and its derived quantities
         const Loc<DIRECT> li = locate<DIRECT>(a.acc, pi);
         R xi, yi, zi, vxi, vyi, vzi, hi, rhoi, omi, ui, ali;
         if constexpr (FP32) {
-            xi = ld_as_f32(a.f[SPHV_X], li, a.g, cell);
-            yi = ld_as_f32(a.f[SPHV_Y], li, a.g, cell);
-            zi = ld_as_f32(a.f[SPHV_Z], li, a.g, cell);
+            // relative to the corner of the item's first cell, as the candidates are staged
+            const int own = a.key_sorted[pi];
+            int ox, oy, oz;
+            cell_coords(own, a.g, ox, oy, oz);
+            xi = ld_as_f32(a.f[SPHV_X], li, a.g, own) + __double2float_rn((double)(ox - kx) * a.g.cell[0]);
+            yi = ld_as_f32(a.f[SPHV_Y], li, a.g, own) + __double2float_rn((double)(oy - ky) * a.g.cell[1]);
+            zi = ld_as_f32(a.f[SPHV_Z], li, a.g, own) + __double2float_rn((double)(oz - kz) * a.g.cell[2]);
             vxi = ld_as_f32(a.f[SPHV_VX], li, a.g, cell);
             vyi = ld_as_f32(a.f[SPHV_VY], li, a.g, cell);
             vzi = ld_as_f32(a.f[SPHV_VZ], li, a.g, cell);
@@ -1179,7 +1198,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         };
 
         if (use_spans) run_window(spans, W, lane, fetch, put, compute);
-        else for_window(a, kx, ky, kz, r, lane, stage, compute);
+        else for_window(a, kx, ky, kz, gx, r, lane, stage, compute);
 
         if constexpr (FP32) {
             ax = (double)fax + (double)cax;

@@ -91,8 +91,12 @@ def test_force_window_is_exact(orc, steps):
     own = np.zeros(nc, dtype=np.int64)
     for c in range(nc):
         if start[c + 1] > start[c]:
-            hm = h[start[c]:start[c + 1]].max()
-            own[c] = max(1, int(np.ceil(2.0 * hm * (1.0 + 1e-12) / cmin)))
+            # 2 h of the cell's largest h rounded up to float, as the kernel folds it
+            H = 2.0 * h[start[c]:start[c + 1]].max()
+            f = np.float32(H)
+            if float(f) < H:
+                f = np.nextafter(f, np.float32(np.inf))
+            own[c] = max(1, int(np.ceil(float(f) * (1.0 + 1e-12) / cmin)))
     exact, Rg = _window_model(w, own)
     assert (rf >= exact).all()
     if Rg <= 4 and all(2 * Rg + 1 <= n for n in w.grid):
