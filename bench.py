@@ -14,6 +14,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -35,6 +36,30 @@ HBM_PEAK = 8.0e12
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_loops_tube64_fp64_counters.md")
+PAIR_SRC = os.path.join(ROOT, "paper_2502_16517_amd", "csrc", "k_pair.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the two pair loops, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or
+    None when that summary was taken on another version of the pair kernels."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    for line in text.splitlines():
+        line = line.strip()
+        if not line.startswith("traffic:"):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+        if kv.get("k_pair.hip sha256/16", kv.get("sha256/16")) != src:
+            return None
+        return {"density": float(kv["density"]), "force": float(kv["force"])}
+    return None
 
 
 def make_stepper(torch, sv, inputs, w, precision, lay):
@@ -153,7 +178,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic kernel for "
                          "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -218,9 +242,8 @@ def main():
     else:
         kern, flops, ms_k = "density", dens_flops, r64["ms_density"]
     achieved = flops / (ms_k / 1e3) / 1e12
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(kern)
+    tr = measured_traffic()
+    traffic = tr[kern] if tr else None
     roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop)", "achieved": achieved,
                 "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VALU / 1e12),
                 "traffic": traffic,

@@ -253,12 +253,16 @@ constexpr int kGroupLen = 6;
 constexpr int kGroupReach = 2;
 constexpr int kRowMax = 1024;   // rows up to this length are staged in LDS and grouped
 
-template <bool WRITE>
-__global__ __launch_bounds__(kWave) void k_row_items(const int32_t* cell_start, const int32_t* reach_d, Geom g,
-                                                     int64_t nrows, int32_t* row_cnt, const int32_t* row_start,
-                                                     int64_t max_items, int4* items, int32_t* meta, DevState* st)
+// One wave per row: lanes stage the row's counts and reaches and, per column x,
+// whether every cell within +-kGroupReach of it (in x, y and z) is sparse;
+// lane 0 then walks the row.  For every cell c it leaves gx[c], the cells
+// covered by the items that start at c (0 inside a run), and nit[c], the number
+// of those items; k_items writes them at the exclusive scan of nit.
+__global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start, const int32_t* reach_d, Geom g,
+                                                      int32_t* nit, int32_t* gxo)
 {
     __shared__ int scnt[kRowMax], srch[kRowMax], scol[kRowMax];
+    __shared__ uint8_t sok[kRowMax];
     const int lane = threadIdx.x;
     const int64_t row = blockIdx.x;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -290,65 +294,81 @@ __global__ __launch_bounds__(kWave) void k_row_items(const int32_t* cell_start, 
             }
             scol[x] = m;
         }
+        __syncthreads();
+        // column x may join a run: its whole +-kGroupReach neighbourhood is sparse
+        for (int x = lane; x < nx; x += kWave) {
+            bool ok = true;
+            for (int d = -kGroupReach; d <= kGroupReach; ++d) {
+                int xx = x + d;
+                if (xx < 0 || xx >= nx) {
+                    if (!g.periodic[0]) continue;
+                    xx = xx < 0 ? xx + nx : xx - nx;
+                }
+                ok = ok && scol[xx] <= kSparse;
+            }
+            sok[x] = ok ? 1 : 0;
+        }
     }
     __syncthreads();
     if (lane != 0) return;
-    // the densest column of the run x0..x1 widened by kGroupReach along x
-    auto sparse_around = [&](int x0, int x1) {
-        for (int x = x0 - kGroupReach; x <= x1 + kGroupReach; ++x) {
-            int xx = x;
-            if (xx < 0 || xx >= nx) {
-                if (!g.periodic[0]) continue;
-                xx = xx < 0 ? xx + nx : xx - nx;
-            }
-            if (scol[xx] > kSparse) return false;
-        }
-        return true;
-    };
-    int64_t o = WRITE ? row_start[row] : 0;
-    int nitems = 0;
+    const bool px_ok = !g.periodic[0] || 2 * kGroupReach + 1 <= nx;
     int x = 0;
     while (x < nx) {
         const int c0 = staged ? scnt[x] : cell_start[base + x + 1] - cell_start[base + x];
-        const bool groupable = staged && c0 <= kSparse && (c0 == 0 || srch[x] <= kGroupReach) &&
-                               (!g.periodic[0] || 2 * kGroupReach + 1 <= nx) && sparse_around(x, x);
+        const bool groupable = staged && px_ok && sok[x] && (c0 == 0 || srch[x] <= kGroupReach);
         if (!groupable) {
-            const int first = cell_start[base + x];
-            for (int f = 0; f < c0; f += kWave) {
-                if (WRITE && o < max_items) items[o] = make_int4((int)(base + x), first + f, min(kWave, c0 - f), 1);
-                ++o;
-                ++nitems;
-            }
+            gxo[base + x] = 1;
+            nit[base + x] = (c0 + kWave - 1) / kWave;
             ++x;
             continue;
         }
         int R = c0 > 0 ? srch[x] : 0, tot = c0, gx = 1;
-        while (x + gx < nx && gx < kGroupLen) {
+        while (x + gx < nx && gx < kGroupLen && sok[x + gx]) {
             const int c2 = scnt[x + gx];
-            if (c2 > kSparse || tot + c2 > kGroupMax) break;
+            if (tot + c2 > kGroupMax) break;
             const int r2 = c2 > 0 ? srch[x + gx] : 0;
             if (r2 > kGroupReach || (c2 > 0 && R > 0 && r2 != R)) break;
             if (g.periodic[0] && 2 * kGroupReach + gx + 1 > nx) break;
-            if (!sparse_around(x, x + gx)) break;
             tot += c2;
             R = R > r2 ? R : r2;
             ++gx;
         }
-        if (tot > 0) {
-            if (WRITE && o < max_items) items[o] = make_int4((int)(base + x), cell_start[base + x], tot, gx);
-            ++o;
-            ++nitems;
+        gxo[base + x] = gx;
+        nit[base + x] = tot > 0 ? 1 : 0;
+        for (int k = 1; k < gx; ++k) {
+            gxo[base + x + k] = 0;
+            nit[base + x + k] = 0;
         }
         x += gx;
     }
-    if (!WRITE) row_cnt[row] = nitems;
-    if (WRITE && row == 0) {
-        int total = row_start[nrows];
+}
+
+__global__ void k_items(const int32_t* cell_start, const int32_t* item_start, const int32_t* gxo, int64_t nc,
+                        int64_t max_items, int4* items, int32_t* meta, DevState* st)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) {
+        int total = item_start[nc];
         if (total > max_items) {
             set_flag(st, SPHV_F_QUEUE_OVERFLOW);
             total = (int)max_items;
         }
         meta[META_NITEMS] = total;
+    }
+    if (c >= nc) return;
+    int o = item_start[c];
+    const int ni = item_start[c + 1] - o;
+    if (ni == 0) return;
+    const int gx = gxo[c];
+    const int b = cell_start[c];
+    if (gx > 1) {
+        if (o < max_items) items[o] = make_int4((int)c, b, cell_start[c + gx] - b, gx);
+        return;
+    }
+    const int e = cell_start[c + 1];
+    for (int f = b; f < e; f += kWave) {
+        if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 1);
+        ++o;
     }
 }
 
@@ -522,11 +542,11 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
                        c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];
-    hipLaunchKernelGGL(k_row_items<false>, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, nrows,
-                       c.tmp_a, (const int32_t*)nullptr, c.max_items, c.items, c.meta, st);
-    if ((e = scan_excl(c.tmp_a, nrows, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_items<true>, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, nrows,
-                       c.tmp_a, (const int32_t*)c.item_start, c.max_items, c.items, c.meta, st);
+    hipLaunchKernelGGL(k_row_groups, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, c.tmp_a,
+                       c.tmp_b);
+    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.tmp_b, c.nc,
+                       c.max_items, c.items, c.meta, st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipGetLastError();
 }
