@@ -14,7 +14,8 @@ constexpr int kWave = 64;
 constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRedBlock = 1024;  // particles per block of the fixed-order reductions
 constexpr int kMaskChunks = 12;  // candidate chunks per work item whose hit masks are cached
-constexpr int kQStride = 32;     // ints between two queue heads: one 128-byte line each
+constexpr int kQStride = 1024;   // ints between two queue heads: one 4 KiB page each, so that their
+                                 // atomics do not queue up at one memory channel
 constexpr int kMaxPairBlocks = 256 * 20;   // largest grid of a pair loop
 constexpr int kPartSlots = 4;    // per-wave counters a pair loop leaves for its fold
 
@@ -94,9 +95,9 @@ enum {
     META_NITEMS = 0,
     META_MASKS = 2,                          // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
     META_RGLOBAL_F = 3,                      // largest own force reach
-    META_QHEAD_D = 64,                       // 8 per-XCD heads of the density queue, kQStride apart
-    META_QHEAD_F = 64 + kNumXcd * kQStride,  // the same for the force queue
-    META_SIZE = 64 + 2 * kNumXcd * kQStride
+    META_QHEAD_D = kQStride,                       // 8 per-XCD heads of the density queue, kQStride apart
+    META_QHEAD_F = kQStride + kNumXcd * kQStride,  // the same for the force queue
+    META_SIZE = kQStride + 2 * kNumXcd * kQStride
 };
 
 // Arguments of the pair kernels.

@@ -34,17 +34,24 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// head[q * kQStride] counts the items taken from queue q (one cache line per head).
-__device__ int next_item(int32_t* head, int n_items, int xcd, int& qoff)
+// head[q * kQStride] counts the items taken from queue q.  A wave drains its
+// own queue (q = its XCD), then looks at no more than kStealProbes of the
+// others, in an order rotated per wave so that stealers spread over them, and
+// stops at the first drained one it finds after those.  Every queue is some
+// waves' own, so every item is taken.  Reads and takes of a head serialise at
+// the device's point of coherence; bounding the probes keeps the end of a
+// launch from queueing thousands of them.
+constexpr int kStealProbes = 3;
+
+__device__ int next_item(int32_t* head, int n_items, int xcd, int rot, int& qoff)
 {
-    while (qoff < kNumXcd) {
-        int q = (xcd + qoff) % kNumXcd;
-        int lo = (int)(((int64_t)n_items * q) / kNumXcd);
-        int hi = (int)(((int64_t)n_items * (q + 1)) / kNumXcd);
+    while (qoff <= kStealProbes) {
+        const int q = qoff == 0 ? xcd : (xcd + 1 + (rot + qoff - 1) % (kNumXcd - 1)) % kNumXcd;
+        const int lo = (int)(((int64_t)n_items * q) / kNumXcd);
+        const int hi = (int)(((int64_t)n_items * (q + 1)) / kNumXcd);
         if (lo < hi) {
             int32_t* hp = &head[q * kQStride];
-            // heads only grow: a queue read as drained is drained, and reading
-            // is cheaper than taking (the takes of one head serialise)
+            // heads only grow: a queue read as drained is drained
             if (lo + __hip_atomic_load(hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
                 const int k = atomicAdd(hp, 1);
                 if (lo + k < hi) return lo + k;
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
     uint32_t flags = 0;
 
     for (;;) {
-        if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, qoff);
+        if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, (int)(blockIdx.x / kNumXcd), qoff);
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
         __syncthreads();
@@ -968,7 +975,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     (void)gm;
 
     for (;;) {
-        if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, qoff);
+        if (lane == 0) s_item = next_item(a.meta + a.qhead, n_items, xcd, (int)(blockIdx.x / kNumXcd), qoff);
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform
         __syncthreads();
