@@ -3,16 +3,17 @@
 // that only neighbouring cells interact; Sec. 5.2: the particles of one cell
 // form one chunk, indexed by CSR-like offsets).
 //
-// Pipeline (all on one stream, no host synchronisation):
-//   fill        counts, hmax, meta := 0
+// Pipeline of cells_build (all on one stream, no host synchronisation):
+//   clear       counts, hmax, meta := 0
 //   bin         key_i, counts[key]++, hmax[key] = max 2 h headroom, flags
 //   scan        cell_start = exclusive scan of counts, cursor = cell_start
 //   place       perm_tmp[cursor[key_i]++] = i       (cell-grouped, any order)
 //   segsort     perm[cell] = ascending record indices of the cell: the stable
-//               order (ties by index), key_sorted, reach_d, item counts
-//   scan        item_start; n_items
-//   items       (cell, first, count <= 64) per 64 particles of a cell
-//   reach_f     separable box max of reach_d over +-R_global cells
+//               order (ties by index), key_sorted, density reach
+//   row groups  per row of cells: runs of sparse cells sharing one work item
+//   scan, items item_start; the items (cell, first, count <= 64, cells); n_items
+// and of the force window, at the start of sph_force, from the converged h:
+//   own reach per cell, separable box maximum over +-R_global, exact window.
 #include "k_common.h"
 
 namespace sphv {
@@ -28,6 +29,29 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < count; i += stride) p[i] = v;
+}
+
+// Zeroes up to three ranges in one launch (a fill kernel, so that captured
+// graphs hold no memset nodes).
+struct Clear3 {
+    uint32_t* p[3];
+    int64_t n[3];
+};
+
+__global__ void k_clear3(Clear3 c)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r = 0; r < 3; ++r)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n[r]; i += stride) c.p[r][i] = 0u;
+}
+
+hipError_t clear3(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2, hipStream_t s)
+{
+    Clear3 c{{p0, p1, p2}, {n0, n1, n2}};
+    const int64_t m = std::max(n0, std::max(n1, n2));
+    const unsigned b = (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_clear3, dim3(b), dim3(256), 0, s, c);
+    return hipGetLastError();
 }
 
 __global__ void k_state_init(DevState* st, int full)
@@ -524,9 +548,8 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
                               hipStream_t s)
 {
     hipError_t e;
-    if ((e = launch_fill_u32(c.counts, 0u, c.nc, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(c.hmax_bits, 0u, c.nc, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(c.meta, 0u, META_SIZE, s)) != hipSuccess) return e;
+    if ((e = clear3((uint32_t*)c.counts, c.nc, c.hmax_bits, c.nc, (uint32_t*)c.meta, META_SIZE, s)) != hipSuccess)
+        return e;
     if (c.n > 0) {
         hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride, g,
                            c.n, c.key, c.counts, c.hmax_bits, st);
@@ -555,8 +578,8 @@ hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t str
                               hipStream_t s)
 {
     hipError_t e;
-    if ((e = launch_fill_u32(c.meta + META_RGLOBAL_F, 0u, 1, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(c.hmax_bits, 0u, c.nc, s)) != hipSuccess) return e;
+    if ((e = clear3((uint32_t*)(c.meta + META_RGLOBAL_F), 1, c.hmax_bits, c.nc, nullptr, 0, s)) != hipSuccess)
+        return e;
     if (c.n > 0) {
         hipLaunchKernelGGL(k_force_hbits, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h, stride, c.n,
                            c.hmax_bits);
