@@ -211,13 +211,34 @@ int32_t sphv_cells_build(sphv_cells* c, const void* aos_dev, const sphv_descript
 int32_t sphv_cells_get_info(const sphv_cells* c, sphv_cells_info* out);
 void sphv_cells_destroy(sphv_cells* c);
 
+/* Records stored cell by cell (paper Sec. 2.2 and Sec. 5.2: the particle sort
+ * may move the records after each drift so that the particles of one cell form
+ * one contiguous chunk of memory).  After sphv_cells_build on c, moves the
+ * whole records (stride bytes each, every member, cold ones included) so that
+ * record p becomes the record that was at perm[p]; then c's perm is the
+ * identity and its key follows the records, so c stays valid for those
+ * records until the next sphv_cells_build.  Stable: particles of one cell keep
+ * their order, so a following cells_build gives the same cells and loops sum
+ * in the same order.  Only views of kind SPHV_LAYOUT_SORTED require it.
+ *   aos_dev  the n records c was built from; base aligned to 4 bytes.
+ *   stride   record bytes, a multiple of 4.
+ *   ws_dev   device scratch of sphv_records_sort_workspace_bytes(stride, n)
+ *            bytes, 256-B aligned; its contents are not kept.
+ * Two kernels on stream (graph-capturable).  Errors: SPHV_E_INVALID_ARG (NULL
+ * handle, stride or alignment), SPHV_E_WORKSPACE, SPHV_E_STATE (c not built). */
+size_t sphv_records_sort_workspace_bytes(uint32_t stride, int64_t n);
+int32_t sphv_records_sort(sphv_cells* c, void* aos_dev, uint32_t stride, void* ws_dev, size_t ws_bytes,
+                          void* stream);
+
 /* ----------------------------------------------------------------- views */
 
 enum {
     SPHV_LAYOUT_SOA = 0,     /* one array per member (Sec. 2.4, Listing 2)           */
     SPHV_LAYOUT_AOSOA = 1,   /* blocks of aosoa_width particles, SoA inside a block  */
-    SPHV_LAYOUT_DIRECT = 2   /* no conversion: loops read and write the records      */
+    SPHV_LAYOUT_DIRECT = 2,  /* no conversion: loops read and write the records      */
                              /* through the index (the paper's unconverted kernels)  */
+    SPHV_LAYOUT_SORTED = 3   /* no conversion, records stored cell by cell          */
+                             /* (sphv_records_sort): element p is record p          */
 };
 enum { SPHV_PREC_FP64 = 0, SPHV_PREC_FP32 = 1 };
 
@@ -325,13 +346,18 @@ int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
  * *best and the medians, in candidate order, to ms (NULL: not reported).
  *
  * candidates: NULL for the built-in set (sphv_autotune_candidates), else an
- *   array of n_candidates (1..64) layouts.
+ *   array of n_candidates (1..128) layouts.
  * Records: every member d names is copied out bit for bit before the first
  *   trial and copied back after each trial and at the end, so the records
  *   leave the call as they came in.  Run it on records that hold a valid
  *   state for the loop (for the force loop: after a density scatter).
+ * SPHV_LAYOUT_SORTED candidates: the trial starts with sphv_records_sort (its
+ *   time counts, as the layout needs it) and afterwards moves the records,
+ *   the cells' perm and key back to where they were, so cells (const for the
+ *   caller) is modified during the call and restored before it returns.
  * ws_dev: device workspace of sphv_autotune_workspace_bytes(...) bytes, 256-B
- *   aligned (state block, bit copy of the members, the largest candidate view).
+ *   aligned (state block, bit copy of the members, the largest candidate view,
+ *   and with sorted candidates a copy of the records and of perm and key).
  * The call synchronises stream (it times on the host) and fails with
  * SPHV_E_STATE while stream is being captured into a graph, SPHV_E_ALIAS if an
  * open view on the same records conflicts with a trial view, SPHV_E_WORKSPACE
@@ -350,6 +376,34 @@ int32_t sphv_autotune(int32_t loop, void* aos_dev, const sphv_descriptor* d, con
                       const sphv_params* p, int32_t precision, const sphv_layout* candidates,
                       int32_t n_candidates, int32_t reps, void* ws_dev, size_t ws_bytes,
                       sphv_layout* best, float* ms, void* stream);
+
+/* Cells per support length, the tuner's grid axis (the mesh of Sec. 2.1 sized
+ * for the largest smoothing length h_ref): along each axis
+ *   grid[a] = max(floor(len[a] k / (2 h_ref 1.1)), 3 if periodic else 1),
+ * i.e. k cells of edge >= 2 h_ref 1.1 / k span one support.  k = 1 gives the
+ * plain 27-cell stencil for particles with h <= h_ref; larger k give smaller
+ * cells and wider (per-cell) windows.  k in 1..4; SPHV_E_UNSUPPORTED beyond
+ * 4096 cells on an axis. */
+int32_t sphv_grid_for(const sphv_params* p, double h_ref, int32_t cells_per_support, int32_t* grid);
+
+/* Picks the grid for the density + force pair.  For each candidate grid
+ * (grids[3g..3g+2], n_grids in 1..16) it times, on stream with HIP events,
+ * reps trials of: cells_build on that grid, then the density view (gather,
+ * loop, scatter) and the force view (gather, loop, scatter) with layouts
+ * l_density and l_force (not SPHV_LAYOUT_SORTED: SPHV_E_UNSUPPORTED).  The
+ * members of d_density and d_force are restored bit for bit after each trial,
+ * as in sphv_autotune; cells_build takes x, y, z, h from d_density.  *best is
+ * the index of the grid with the smallest median, ms the medians (NULL: not
+ * reported).  The caller then builds its own cells with that grid.  Host
+ * timing: synchronises stream, SPHV_E_STATE under graph capture. */
+size_t sphv_autotune_grid_workspace_bytes(const sphv_descriptor* d_density, const sphv_descriptor* d_force,
+                                          int64_t n, const sphv_params* p, int32_t precision,
+                                          const sphv_layout* l_density, const sphv_layout* l_force,
+                                          const int32_t* grids, int32_t n_grids);
+int32_t sphv_autotune_grid(void* aos_dev, const sphv_descriptor* d_density, const sphv_descriptor* d_force,
+                           int64_t n, const sphv_params* p, int32_t precision, const sphv_layout* l_density,
+                           const sphv_layout* l_force, const int32_t* grids, int32_t n_grids, int32_t reps,
+                           void* ws_dev, size_t ws_bytes, int32_t* best, float* ms, void* stream);
 
 /* ---------------------------------------------------------------- graphs */
 

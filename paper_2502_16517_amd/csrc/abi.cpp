@@ -125,6 +125,7 @@ struct sphv_cells {
     CellsDev dev;
     sphv_params params;
     bool built = false;
+    bool sorted = false;   // records moved into cell order since the last build
 };
 
 struct FieldPlan {
@@ -325,10 +326,13 @@ uint64_t view_bytes_of(const sphv_view* v)
     return v->fields_bytes + align_up(nred * 16 * sizeof(double), kAlign);
 }
 
+// layouts whose loops run on the records themselves (no explicit storage)
+bool is_direct(uint32_t kind) { return kind == SPHV_LAYOUT_DIRECT || kind == SPHV_LAYOUT_SORTED; }
+
 int32_t check_layout(const sphv_layout* l, int32_t precision)
 {
     if (!l) return SPHV_E_INVALID_ARG;
-    if (l->kind > SPHV_LAYOUT_DIRECT) return SPHV_E_INVALID_ARG;
+    if (l->kind > SPHV_LAYOUT_SORTED) return SPHV_E_INVALID_ARG;
     if (l->kind == SPHV_LAYOUT_AOSOA && (!is_pow2(l->aosoa_width) || l->aosoa_width < 8 || l->aosoa_width > 1024))
         return SPHV_E_INVALID_ARG;
     if (l->tpi > 64) return SPHV_E_INVALID_ARG;
@@ -470,9 +474,33 @@ int32_t sphv_cells_build(sphv_cells* c, const void* aos, const sphv_descriptor* 
     }
     Access rec = acc_rec(nullptr, d->stride);
     Geom g = geom_of(&c->params);
+    c->sorted = false;
     hipError_t e = launch_cells_build(c->dev, f, rec, g, (DevState*)state, (hipStream_t)stream);
     if (e != hipSuccess) return SPHV_E_HIP;
     c->built = true;
+    return SPHV_OK;
+}
+
+size_t sphv_records_sort_workspace_bytes(uint32_t stride, int64_t n)
+{
+    if (stride == 0 || stride % 4 || n < 0) return 0;
+    return (size_t)align_up((uint64_t)stride * (uint64_t)std::max<int64_t>(n, 1), kAlign);
+}
+
+int32_t sphv_records_sort(sphv_cells* c, void* aos, uint32_t stride, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!c || stride == 0 || stride % 4 || (uintptr_t)aos % 4) return SPHV_E_INVALID_ARG;
+    const int64_t n = c->dev.n;
+    if (n > 0 && !aos) return SPHV_E_INVALID_ARG;
+    if (!ws || (uintptr_t)ws % kAlign || ws_bytes < sphv_records_sort_workspace_bytes(stride, n))
+        return SPHV_E_WORKSPACE;
+    if (!c->built) return SPHV_E_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    // sorted copy in the workspace, then back over the records in storage order
+    if (launch_rec_move(aos, ws, c->dev.perm, nullptr, stride, n, s) != hipSuccess) return SPHV_E_HIP;
+    if (launch_rec_move(ws, aos, nullptr, nullptr, stride, n, s) != hipSuccess) return SPHV_E_HIP;
+    if (launch_sorted_index(c->dev.perm, c->dev.key, c->dev.key_sorted, n, s) != hipSuccess) return SPHV_E_HIP;
+    c->sorted = true;
     return SPHV_OK;
 }
 
@@ -543,7 +571,7 @@ int32_t sphv_view_field(const sphv_view* v, uint32_t k, void** ptr, int32_t* dty
 {
     if (!v || !ptr || !dtype || !block_len || !block_bytes) return SPHV_E_INVALID_ARG;
     if (k >= v->plan.size()) return SPHV_E_INVALID_ARG;
-    if (v->layout.kind == SPHV_LAYOUT_DIRECT) return SPHV_E_UNSUPPORTED;
+    if (is_direct(v->layout.kind)) return SPHV_E_UNSUPPORTED;
     *ptr = v->ws + v->plan[k].view_off;
     *dtype = (int32_t)v->plan[k].view_dtype;
     *block_len = v->layout.kind == SPHV_LAYOUT_SOA ? (uint64_t)v->n : v->block_len;
@@ -559,7 +587,7 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     for (const FieldPlan& p : v->plan) needs_cells |= p.rel_axis >= 0;
     if (needs_cells && (!cells || !cells->built || cells->dev.n != v->n || v->index != cells->dev.perm))
         return SPHV_E_STATE;
-    if (v->layout.kind != SPHV_LAYOUT_DIRECT) {
+    if (!is_direct(v->layout.kind)) {
         std::lock_guard<std::mutex> lk(g_open_mutex);
         for (sphv_view* o : g_open)
             if (views_conflict(v, o)) return SPHV_E_ALIAS;
@@ -567,7 +595,7 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     }
     v->open = 1;
     v->gathered = 1;
-    if (v->layout.kind == SPHV_LAYOUT_DIRECT || v->n == 0) return SPHV_OK;
+    if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;
     FieldRef src[kMaxFields], dst[kMaxFields];
     int nf = 0;
     for (const FieldPlan& p : v->plan) {
@@ -597,7 +625,7 @@ int32_t sphv_soa_to_aos(sphv_view* v, void* stream)
         g_open.erase(std::remove(g_open.begin(), g_open.end(), v), g_open.end());
     }
     v->open = 0;
-    if (v->layout.kind == SPHV_LAYOUT_DIRECT || v->n == 0) return SPHV_OK;
+    if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;
     FieldRef src[kMaxFields], dst[kMaxFields];
     int nf = 0;
     for (const FieldPlan& p : v->plan) {
@@ -636,7 +664,10 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     for (int k = 0; k < nin; ++k) if (int32_t s = need(v, roles_in[k], SPHV_IN)) return s;
     for (int k = 0; k < nout; ++k) if (int32_t s = need(v, roles_out[k], SPHV_OUT)) return s;
     std::memset(a, 0, sizeof(*a));
-    bool direct = v->layout.kind == SPHV_LAYOUT_DIRECT;
+    bool direct = is_direct(v->layout.kind);
+    // a view over records stored cell by cell indexes them in storage order
+    const bool sorted = v->layout.kind == SPHV_LAYOUT_SORTED;
+    if (sorted && !c->sorted) return SPHV_E_STATE;
     for (int r = 1; r < SPHV_NROLES; ++r) {
         int k = v->role_field[r];
         if (k < 0) continue;
@@ -649,7 +680,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
         a->f[SPHV_Y].rel_axis = 1;
         a->f[SPHV_Z].rel_axis = 2;
     }
-    a->acc = direct ? acc_rec(v->index, v->desc.stride) : acc_view(v);
+    a->acc = direct ? acc_rec(sorted ? nullptr : v->index, v->desc.stride) : acc_view(v);
     a->g = geom_of(p);
     a->items = c->dev.items;
     a->cell_start = c->dev.cell_start;
@@ -685,7 +716,7 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     if (v->n == 0) return SPHV_OK;
     a.reach = c->dev.reach_d;
     a.qhead = META_QHEAD_D;
-    return hip_status(launch_density(a, v->layout.kind == SPHV_LAYOUT_DIRECT, v->precision == SPHV_PREC_FP32,
+    return hip_status(launch_density(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
                                      (int)v->layout.masked, (hipStream_t)stream));
 }
 
@@ -704,7 +735,7 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     a.reach_s = c->dev.reach_s;
     a.qhead = META_QHEAD_F;
     hipStream_t st = (hipStream_t)stream;
-    bool direct = v->layout.kind == SPHV_LAYOUT_DIRECT;
+    bool direct = is_direct(v->layout.kind);
     // windows from the converged h: members a view only reads are never
     // modified while it is open, so the records hold them
     const FieldRef hrec = ref_rec(v->aos, v->plan[v->role_field[SPHV_H]].f);
@@ -725,7 +756,7 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
     if (v->n == 0) return SPHV_OK;
     // inputs from the records (A_in members are never modified while the view
     // is open), outputs from where the loop wrote them
-    const bool direct = v->layout.kind == SPHV_LAYOUT_DIRECT;
+    const bool direct = is_direct(v->layout.kind);
     FieldRef in6[6], out5[5];
     for (int k = 0; k < 6; ++k) in6[k] = ref_rec(v->aos, v->plan[v->role_field[rin[k]]].f);
     for (int k = 0; k < 5; ++k) {
@@ -806,3 +837,9 @@ void sphv_graph_destroy(sphv_graph* g)
 }
 
 }  // extern "C"
+
+namespace sphv {
+CellsDev* cells_dev(sphv_cells* c) { return &c->dev; }
+bool cells_sorted(const sphv_cells* c) { return c->sorted; }
+void cells_set_sorted(sphv_cells* c, bool sorted) { c->sorted = sorted; }
+}  // namespace sphv

@@ -146,7 +146,19 @@ hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hip
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
                                const Access& outacc, int out_direct, DevState* st, double cfl, int64_t n,
                                double* partials, hipStream_t s);
+// whole records: dst[didx ? didx[p] : p] = src[sidx ? sidx[p] : p], stride bytes
+// each (stride and both bases multiples of 4 bytes)
+hipError_t launch_rec_move(const void* src, void* dst, const int32_t* sidx, const int32_t* didx,
+                           uint32_t stride, int64_t n, hipStream_t s);
+// perm[p] = p, key[p] = key_sorted[p]
+hipError_t launch_sorted_index(int32_t* perm, int32_t* key, const int32_t* key_sorted, int64_t n,
+                               hipStream_t s);
 hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g,
                              const DevState* st, int64_t n, hipStream_t s);
 int pair_grid_blocks(int64_t max_items);
+// the parts of a cells handle that the tuner saves and puts back around its
+// trials on records stored cell by cell (abi.cpp)
+CellsDev* cells_dev(sphv_cells* c);
+bool cells_sorted(const sphv_cells* c);
+void cells_set_sorted(sphv_cells* c, bool sorted);
 }  // namespace sphv

@@ -6,6 +6,8 @@
 //         the lower corner of their cell).
 // scatter (epilogue, C^T o W): record[index[p]].f = view[p].f for f in A_out only.
 // kick_drift: per record, every product and sum rounded on its own.
+#include <algorithm>
+
 #include "k_common.h"
 
 namespace sphv {
@@ -99,7 +101,67 @@ __global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kConvThreads - 1) / kConvThreads); }
 
+// Whole-record move: record (didx ? didx[p] : p) of dst = record (sidx ? sidx[p]
+// : p) of src, as wpr words of W.  Consecutive threads take consecutive words
+// of one record, so each record is one contiguous read and one contiguous
+// write; a grid-stride loop covers n * wpr words.
+template <typename W>
+__global__ __launch_bounds__(kConvThreads) void k_rec_move(const W* __restrict__ src, W* __restrict__ dst,
+                                                           const int32_t* sidx, const int32_t* didx,
+                                                           uint32_t wpr, int64_t n)
+{
+    const int64_t total = n * (int64_t)wpr;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += step) {
+        const int64_t p = t / wpr;
+        const int64_t w = t - p * wpr;
+        const int64_t rs = sidx ? (int64_t)sidx[p] : p;
+        const int64_t rd = didx ? (int64_t)didx[p] : p;
+        dst[rd * wpr + w] = src[rs * wpr + w];
+    }
+}
+
+// After the records were moved into sorted order: perm is the identity and the
+// key of record p is the cell of sorted position p.
+__global__ __launch_bounds__(kConvThreads) void k_sorted_index(int32_t* perm, int32_t* key,
+                                                               const int32_t* key_sorted, int64_t n)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    perm[p] = (int32_t)p;
+    key[p] = key_sorted[p];
+}
+
+template <typename W>
+hipError_t rec_move_as(const void* src, void* dst, const int32_t* sidx, const int32_t* didx, uint32_t stride,
+                       int64_t n, hipStream_t s)
+{
+    const uint32_t wpr = stride / (uint32_t)sizeof(W);
+    const int64_t total = n * (int64_t)wpr;
+    const int64_t blocks = std::min<int64_t>((total + kConvThreads - 1) / kConvThreads, 1 << 20);
+    hipLaunchKernelGGL(k_rec_move<W>, dim3((unsigned)blocks), dim3(kConvThreads), 0, s, (const W*)src, (W*)dst,
+                       sidx, didx, wpr, n);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_rec_move(const void* src, void* dst, const int32_t* sidx, const int32_t* didx, uint32_t stride,
+                           int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const uintptr_t al = (uintptr_t)src | (uintptr_t)dst | stride;
+    if (al % 16 == 0) return rec_move_as<uint4>(src, dst, sidx, didx, stride, n, s);
+    if (al % 8 == 0) return rec_move_as<uint2>(src, dst, sidx, didx, stride, n, s);
+    return rec_move_as<uint32_t>(src, dst, sidx, didx, stride, n, s);
+}
+
+hipError_t launch_sorted_index(int32_t* perm, int32_t* key, const int32_t* key_sorted, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sorted_index, dim3(nblk(n)), dim3(kConvThreads), 0, s, perm, key, key_sorted, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& sa, const Access& da,
                          const int32_t* cell_key, const Geom& g, int64_t n, hipStream_t s)

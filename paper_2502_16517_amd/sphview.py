@@ -24,7 +24,7 @@ F_NONFINITE_INPUT, F_H_NOT_CONVERGED, F_H_CAP_HIT, F_QUEUE_OVERFLOW = 1, 2, 4, 8
 F_NONFINITE_OUTPUT, F_GRID_TOO_SMALL, F_OUT_OF_BOX = 16, 32, 64
 F64, F32, I64, I32 = 1, 2, 3, 4
 IN, OUT, INOUT = 1, 2, 3
-LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT = 0, 1, 2
+LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT, LAYOUT_SORTED = 0, 1, 2, 3
 PREC_FP64, PREC_FP32 = 0, 1
 LOOP_DENSITY, LOOP_FORCE = 0, 1
 
@@ -39,7 +39,8 @@ EXPORTS = [
     "sphv_view_create", "sphv_aos_to_soa", "sphv_soa_to_aos", "sphv_view_field", "sphv_view_destroy",
     "sphv_sph_density", "sphv_sph_force", "sphv_step_reduce", "sphv_kick_drift", "sphv_graph_begin", "sphv_graph_end",
     "sphv_graph_launch", "sphv_graph_destroy", "sphv_autotune_candidates", "sphv_autotune_workspace_bytes",
-    "sphv_autotune",
+    "sphv_autotune", "sphv_records_sort_workspace_bytes", "sphv_records_sort", "sphv_grid_for",
+    "sphv_autotune_grid_workspace_bytes", "sphv_autotune_grid",
 ]
 
 
@@ -132,6 +133,17 @@ def lib():
         "sphv_autotune": (C.c_int32, [C.c_int32, VP, C.POINTER(Descriptor), VP, C.POINTER(Params), C.c_int32,
                                       C.POINTER(Layout), C.c_int32, C.c_int32, VP, C.c_size_t,
                                       C.POINTER(Layout), C.POINTER(C.c_float), VP]),
+        "sphv_records_sort_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_int64]),
+        "sphv_records_sort": (C.c_int32, [VP, VP, C.c_uint32, VP, C.c_size_t, VP]),
+        "sphv_grid_for": (C.c_int32, [C.POINTER(Params), C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+        "sphv_autotune_grid_workspace_bytes": (C.c_size_t, [C.POINTER(Descriptor), C.POINTER(Descriptor),
+                                                            C.c_int64, C.POINTER(Params), C.c_int32,
+                                                            C.POINTER(Layout), C.POINTER(Layout),
+                                                            C.POINTER(C.c_int32), C.c_int32]),
+        "sphv_autotune_grid": (C.c_int32, [VP, C.POINTER(Descriptor), C.POINTER(Descriptor), C.c_int64,
+                                           C.POINTER(Params), C.c_int32, C.POINTER(Layout), C.POINTER(Layout),
+                                           C.POINTER(C.c_int32), C.c_int32, C.c_int32, VP, C.c_size_t,
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_float), VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -293,6 +305,16 @@ def cells_destroy(cells):
     lib().sphv_cells_destroy(cells)
 
 
+def records_sort_workspace_bytes(stride: int, n: int) -> int:
+    return int(lib().sphv_records_sort_workspace_bytes(stride, n))
+
+
+def records_sort(cells, aos, stride: int, ws, stream=None, ws_bytes: int | None = None):
+    """Moves the records into the cells' sorted order (whole records)."""
+    nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
+    _chk(lib().sphv_records_sort(cells, _ptr(aos), stride, _ptr(ws), nb, _stream(stream)), "records_sort")
+
+
 # ------------------------------------------------------------ views
 
 def view_workspace_bytes(d: Descriptor, n: int, l: Layout, precision: int) -> int:
@@ -398,8 +420,44 @@ def autotune(loop: int, aos, d: Descriptor, cells, p: Params, precision: int, ws
     return best, [(c, float(ms[i])) for i, c in enumerate(cands)]
 
 
+def grid_for(p: Params, h_ref: float, cells_per_support: int) -> tuple:
+    """Cells per axis with cells_per_support cells across the support 2 h_ref."""
+    g = (C.c_int32 * 3)()
+    _chk(lib().sphv_grid_for(C.byref(p), h_ref, cells_per_support, g), "grid_for")
+    return tuple(int(v) for v in g)
+
+
+def _grid_array(grids):
+    flat = [int(v) for g in grids for v in g]
+    return (C.c_int32 * len(flat))(*flat), len(grids)
+
+
+def autotune_grid_workspace_bytes(d_density: Descriptor, d_force: Descriptor, n: int, p: Params, precision: int,
+                                  l_density: Layout, l_force: Layout, grids) -> int:
+    arr, k = _grid_array(grids)
+    return int(lib().sphv_autotune_grid_workspace_bytes(C.byref(d_density), C.byref(d_force), n, C.byref(p),
+                                                        precision, C.byref(l_density), C.byref(l_force), arr, k))
+
+
+def autotune_grid(aos, d_density: Descriptor, d_force: Descriptor, n: int, p: Params, precision: int,
+                  l_density: Layout, l_force: Layout, grids, ws, reps: int = 3, stream=None,
+                  ws_bytes: int | None = None):
+    """Times cells_build + density + force on every grid; returns (index of the
+    fastest, list of (grid, median ms))."""
+    grids = [tuple(g) for g in grids]
+    arr, k = _grid_array(grids)
+    ms = (C.c_float * k)()
+    best = C.c_int32(-1)
+    nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
+    _chk(lib().sphv_autotune_grid(_ptr(aos), C.byref(d_density), C.byref(d_force), n, C.byref(p), precision,
+                                  C.byref(l_density), C.byref(l_force), arr, k, reps, _ptr(ws), nb,
+                                  C.byref(best), ms, _stream(stream)), "autotune_grid")
+    return int(best.value), [(g, float(ms[i])) for i, g in enumerate(grids)]
+
+
 def layout_name(l: Layout) -> str:
-    kind = {LAYOUT_SOA: "soa", LAYOUT_AOSOA: f"aosoa{l.aosoa_width}", LAYOUT_DIRECT: "direct"}[l.kind]
+    kind = {LAYOUT_SOA: "soa", LAYOUT_AOSOA: f"aosoa{l.aosoa_width}", LAYOUT_DIRECT: "direct",
+            LAYOUT_SORTED: "sorted"}[l.kind]
     return f"{kind}/tpi{l.tpi or 'auto'}/{'masked' if l.masked else 'branch'}"
 
 
@@ -411,13 +469,16 @@ class Stepper:
     the force view (gather, force + dt + sums, scatter) and kick_drift.
 
     layout_density / layout_force: Layout of each view (SPHV_LAYOUT_DIRECT runs
-    the loops on the records themselves).  aos may be an (n*256,) uint8 device
-    tensor holding 256-byte records, or None to upload ``rec``.
+    the loops on the records themselves, SPHV_LAYOUT_SORTED on records moved
+    into cell order after each cells_build).  sort_records: move the records
+    into cell order after each cells_build (implied by a SORTED layout).  aos
+    may be an (n*256,) uint8 device tensor holding 256-byte records, or None to
+    upload ``rec``.
     """
 
     def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
                  layout_density: Layout | None = None, layout_force: Layout | None = None,
-                 device="cuda", aos=None, stream=None):
+                 device="cuda", aos=None, stream=None, sort_records: bool = False):
         import torch
         self.torch = torch
         self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
@@ -425,6 +486,8 @@ class Stepper:
         self.precision = precision
         self.ld = layout_density or layout()
         self.lf = layout_force or layout()
+        self.sort_always = sort_records
+        self.sort_ws = None
         self.stream = stream
         self.device = device
         if aos is None:
@@ -432,25 +495,37 @@ class Stepper:
         self.aos = aos
         u8 = dict(dtype=torch.uint8, device=device)
         self.state = torch.zeros(state_bytes(), **u8)
-        self.cells_ws = torch.empty(max(256, cells_workspace_bytes(self.n, params)), **u8)
-        self.cells = cells_create(self.n, params, self.cells_ws)
         self.d_cells = cells_descriptor()
         self.d_dens = density_descriptor()
         self.d_force = force_descriptor()
         self.d_kick = kick_descriptor()
-        self.ws_dens = torch.empty(max(256, view_workspace_bytes(self.d_dens, self.n, self.ld, precision)), **u8)
-        self.ws_force = torch.empty(max(256, view_workspace_bytes(self.d_force, self.n, self.lf, precision)), **u8)
-        info = cells_get_info(self.cells)
-        self.perm_ptr = info.perm
-        self.v_dens = view_create(self.d_dens, self.n, self.ld, precision, self.aos, self.perm_ptr, self.ws_dens)
-        self.v_force = view_create(self.d_force, self.n, self.lf, precision, self.aos, self.perm_ptr,
-                                   self.ws_force)
+        self.v_dens = self.v_force = self.cells = None
+        self._make_cells()
+        self.set_layouts(self.ld, self.lf)
         state_init(self.state, self.stream)
+
+    def _make_cells(self):
+        u8 = dict(dtype=self.torch.uint8, device=self.device)
+        self.cells_ws = self.torch.empty(max(256, cells_workspace_bytes(self.n, self.p)), **u8)
+        self.cells = cells_create(self.n, self.p, self.cells_ws)
+        self.perm_ptr = cells_get_info(self.cells).perm
+
+    @property
+    def sorting(self) -> bool:
+        return self.sort_always or LAYOUT_SORTED in (self.ld.kind, self.lf.kind)
 
     # the pieces of a step, in order
     def build(self):
         begin_step(self.state, self.stream)
         cells_build(self.cells, self.aos, self.d_cells, self.state, self.stream)
+        if self.sorting:
+            self._sort_workspace()
+            records_sort(self.cells, self.aos, inputs.STRIDE, self.sort_ws, self.stream)
+
+    def _sort_workspace(self):
+        if self.sort_ws is None:
+            nb = records_sort_workspace_bytes(inputs.STRIDE, self.n)
+            self.sort_ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)
 
     def density(self):
         aos_to_soa(self.v_dens, self.cells, self.stream)
@@ -479,7 +554,8 @@ class Stepper:
         """Re-plans the views (no view may be open)."""
         u8 = dict(dtype=self.torch.uint8, device=self.device)
         if layout_density is not None:
-            view_destroy(self.v_dens)
+            if self.v_dens:
+                view_destroy(self.v_dens)
             self.v_dens = None
             self.ld = layout_density
             self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_dens, self.n, self.ld,
@@ -487,20 +563,62 @@ class Stepper:
             self.v_dens = view_create(self.d_dens, self.n, self.ld, self.precision, self.aos, self.perm_ptr,
                                       self.ws_dens)
         if layout_force is not None:
-            view_destroy(self.v_force)
+            if self.v_force:
+                view_destroy(self.v_force)
             self.v_force = None
             self.lf = layout_force
             self.ws_force = self.torch.empty(max(256, view_workspace_bytes(self.d_force, self.n, self.lf,
                                                                            self.precision)), **u8)
             self.v_force = view_create(self.d_force, self.n, self.lf, self.precision, self.aos, self.perm_ptr,
                                        self.ws_force)
+        if self.sorting:
+            self._sort_workspace()      # allocated here, never inside a graph capture
 
-    def autotune(self, candidates=None, reps: int = 3):
+    def set_grid(self, grid):
+        """Re-plans cells and views for another grid (no view may be open)."""
+        for v in (self.v_dens, self.v_force):
+            if v:
+                view_destroy(v)
+        self.v_dens = self.v_force = None
+        cells_destroy(self.cells)
+        self.cells = None
+        q = params_init(tuple(self.p.lo), tuple(self.p.len), tuple(int(g) for g in grid), tuple(self.p.periodic))
+        for name in ("gamma", "eta", "cfl", "h_tol", "headroom", "max_iter"):
+            setattr(q, name, getattr(self.p, name))
+        self.p = q
+        self._make_cells()
+        self.set_layouts(self.ld, self.lf)
+
+    def autotune(self, candidates=None, reps: int = 3, cells_per_support=None, h_ref: float | None = None):
         """Picks the density and the force layouts on the current records (run
         after at least one step, so the force inputs are valid) and re-plans
-        both views with them.  Returns {"density": (best, table), "force": ...}."""
-        self.build()
+        both views with them.  With cells_per_support (e.g. (1, 2)) it first
+        picks the grid among sphv_grid_for(h_ref, k) for those k, h_ref
+        defaulting to the records' largest h, and rebuilds the cells on it.
+        Returns {"density": (best, table), "force": ..., ["grid": ...]}."""
         out = {}
+        if cells_per_support:
+            if h_ref is None:
+                h_ref = float(self.records()[:, inputs.SLOT["h"]].max())
+            grids = []
+            for k in cells_per_support:
+                g = grid_for(self.p, h_ref, int(k))
+                if g not in grids:
+                    grids.append(g)
+            if tuple(self.p.grid) not in grids:
+                grids.append(tuple(self.p.grid))
+            ld = self.ld if self.ld.kind != LAYOUT_SORTED else layout()
+            lf = self.lf if self.lf.kind != LAYOUT_SORTED else layout()
+            nb = autotune_grid_workspace_bytes(self.d_dens, self.d_force, self.n, self.p, self.precision, ld, lf,
+                                               grids)
+            ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)
+            best, table = autotune_grid(self.aos, self.d_dens, self.d_force, self.n, self.p, self.precision, ld, lf,
+                                        grids, ws, reps, self.stream)
+            del ws
+            out["grid"] = (grids[best], table)
+            if grids[best] != tuple(self.p.grid):
+                self.set_grid(grids[best])
+        self.build()
         for loop, d, key in ((LOOP_DENSITY, self.d_dens, "density"), (LOOP_FORCE, self.d_force, "force")):
             nb = autotune_workspace_bytes(d, self.n, self.precision, candidates)
             ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)

@@ -3,6 +3,7 @@ every entry point that include/sphview.h declares, and its host logic (status
 strings, parameter set-up, descriptor validation, workspace planning, the
 open-view alias rule) behaves as documented.  No device work is enqueued."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -202,20 +203,28 @@ def test_loop_calls_need_an_open_view_and_built_cells():
 
 def test_autotune_candidates_and_workspace():
     cands = sv.autotune_candidates()
-    # 6 layouts (SoA, AoSoA 8..64, records) x lanes per particle {auto,1,2,4,8} x {branch, masked}
-    assert len(cands) == 60
+    # 7 layouts (SoA, AoSoA 8..64, records, sorted records) x lanes per particle
+    # {auto,1,2,4,8} x {branch, masked}
+    assert len(cands) == 70
     kinds = {(c.kind, c.aosoa_width) for c in cands}
-    assert kinds == {(sv.LAYOUT_SOA, 0), (sv.LAYOUT_DIRECT, 0)} | {(sv.LAYOUT_AOSOA, w) for w in (8, 16, 32, 64)}
+    assert kinds == {(sv.LAYOUT_SOA, 0), (sv.LAYOUT_DIRECT, 0), (sv.LAYOUT_SORTED, 0)} | \
+        {(sv.LAYOUT_AOSOA, w) for w in (8, 16, 32, 64)}
     assert {c.tpi for c in cands} == {0, 1, 2, 4, 8} and {c.masked for c in cands} == {0, 1}
     n = 1000
+    up = lambda b: -(-b // 256) * 256
+    # sorted candidates add a copy of the records and of perm and key
+    sort_extra = up(n * 256) + 2 * up(4 * n)
     for d in (sv.density_descriptor(), sv.force_descriptor()):
         for prec in (sv.PREC_FP64, sv.PREC_FP32):
             views = max(sv.view_workspace_bytes(d, n, c, prec) for c in cands)
-            backup = sum(-(-n * 8 // 256) * 256 for _ in range(d.n_fields))
-            assert sv.autotune_workspace_bytes(d, n, prec) == 256 + backup + -(-views // 256) * 256
+            backup = sum(up(n * 8) for _ in range(d.n_fields))
+            assert sv.autotune_workspace_bytes(d, n, prec) == 256 + backup + up(views) + sort_extra
             one = [sv.layout(sv.LAYOUT_DIRECT)]
             assert sv.autotune_workspace_bytes(d, n, prec, one) == 256 + backup + \
-                -(-sv.view_workspace_bytes(d, n, one[0], prec) // 256) * 256
+                up(sv.view_workspace_bytes(d, n, one[0], prec))
+            srt = [sv.layout(sv.LAYOUT_SORTED)]
+            assert sv.autotune_workspace_bytes(d, n, prec, srt) == 256 + backup + \
+                up(sv.view_workspace_bytes(d, n, srt[0], prec)) + sort_extra
     assert sv.autotune_workspace_bytes(sv.density_descriptor(), n, sv.PREC_FP64, [sv.layout(tpi=65)]) == 0
 
 
@@ -235,3 +244,79 @@ def test_autotune_argument_errors():
         sv.autotune(0, fake, d, cells, p, sv.PREC_FP64, fake, candidates=[sv.layout(kind=9)], ws_bytes=need)
     assert e.value.status == sv.E_INVALID_ARG
     sv.cells_destroy(cells)
+
+
+def test_records_sort_workspace_and_errors():
+    assert sv.records_sort_workspace_bytes(256, 1000) == 256 * 1000
+    assert sv.records_sort_workspace_bytes(12, 1000) == -(-12 * 1000 // 256) * 256
+    assert sv.records_sort_workspace_bytes(256, 0) == 256
+    assert sv.records_sort_workspace_bytes(6, 10) == 0 and sv.records_sort_workspace_bytes(0, 10) == 0
+    fake = 1 << 40
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    cells = sv.cells_create(10, p, fake, sv.cells_workspace_bytes(10, p))
+    need = sv.records_sort_workspace_bytes(256, 10)
+    # argument checks, then the workspace, then the state (cells never built): no device work
+    for stride, aos, ws, nb, status in ((6, fake, fake, need, sv.E_INVALID_ARG), (256, fake + 2, fake, need,
+                                                                                   sv.E_INVALID_ARG),
+                                       (256, fake, fake, need - 1, sv.E_WORKSPACE),
+                                       (256, fake, fake + 64, need, sv.E_WORKSPACE),
+                                       (256, fake, fake, need, sv.E_STATE)):
+        with pytest.raises(sv.SphvError) as e:
+            sv.records_sort(cells, aos, stride, ws, ws_bytes=nb)
+        assert e.value.status == status
+    sv.cells_destroy(cells)
+    d = sv.density_descriptor()
+    # a sorted view plans no storage, like the view over the records
+    assert sv.view_workspace_bytes(d, 100, sv.layout(sv.LAYOUT_SORTED), sv.PREC_FP64) == \
+        sv.view_workspace_bytes(d, 100, sv.layout(sv.LAYOUT_DIRECT), sv.PREC_FP64)
+    assert sv.view_workspace_bytes(d, 100, sv.layout(kind=4), sv.PREC_FP64) == 0
+
+
+def test_grid_for_matches_the_cell_sizing_rule():
+    """k cells per support 2 h_ref (10 % headroom): k = 1 is the rule the
+    synthetic workloads are generated with; k = 2 halves the cell edge."""
+    for w in (inputs.lattice_box(16, 1), inputs.two_state_tube(8, 2)):
+        p = sv.params_for(w)
+        h = float(w.rec[:, inputs.SLOT["h"]].max())
+        assert sv.grid_for(p, h, 1) == inputs.grid_for(w.length, h, w.periodic)
+        assert sv.grid_for(p, h / 2, 1) == sv.grid_for(p, h, 2)
+        for a, g in enumerate(sv.grid_for(p, h, 2)):
+            assert g == max(math.floor(w.length[a] * 2 / (2 * h * 1.1)), 3 if w.periodic[a] else 1)
+    # the two grids of the two-state tube: sized by its largest h, and by the left state's h
+    w = inputs.two_state_tube(16, 3)
+    p = sv.params_for(w)
+    h = w.rec[:, inputs.SLOT["h"]]
+    assert sv.grid_for(p, float(h.max()), 2) == tuple(w.grid)
+    assert sv.grid_for(p, float(h.max()), 1) == tuple(inputs.two_state_tube(16, 3, fine_grid=False).grid)
+    for hr, k in ((0.0, 1), (-1.0, 1), (float("nan"), 1), (0.1, 0), (0.1, 5)):
+        with pytest.raises(sv.SphvError):
+            sv.grid_for(p, hr, k)
+    with pytest.raises(sv.SphvError) as e:
+        sv.grid_for(p, 1e-9, 1)
+    assert e.value.status == sv.E_UNSUPPORTED
+
+
+def test_autotune_grid_workspace_and_errors():
+    n = 500
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    dd, df = sv.density_descriptor(), sv.force_descriptor()
+    l = sv.layout()
+    grids = [(6, 6, 6), (12, 12, 12)]
+    up = lambda b: -(-b // 256) * 256
+    cells = max(sv.cells_workspace_bytes(n, sv.params_init((0, 0, 0), (1, 1, 1), g, (1, 1, 1))) for g in grids)
+    backup = sum(up(n * 8) for _ in range(dd.n_fields)) + sum(up(n * 8) for _ in range(df.n_fields))
+    need = sv.autotune_grid_workspace_bytes(dd, df, n, p, sv.PREC_FP64, l, l, grids)
+    assert need == 256 + backup + up(cells) + up(sv.view_workspace_bytes(dd, n, l, sv.PREC_FP64)) + \
+        up(sv.view_workspace_bytes(df, n, l, sv.PREC_FP64))
+    assert sv.autotune_grid_workspace_bytes(dd, df, n, p, sv.PREC_FP64, l, l, [(6, 0, 6)]) == 0
+    assert sv.autotune_grid_workspace_bytes(dd, df, n, p, sv.PREC_FP64, l, l, [(6, 6, 6)] * 17) == 0
+    fake = 1 << 40
+    cases = ((l, grids, 3, need, sv.E_INVALID_ARG, 0), (sv.layout(sv.LAYOUT_SORTED), grids, 3, need,
+                                                          sv.E_UNSUPPORTED, 1),
+             (l, grids, 3, need - 1, sv.E_WORKSPACE, 1), (l, [], 3, need, sv.E_INVALID_ARG, 1),
+             (l, grids, 0, need, sv.E_INVALID_ARG, 1))
+    for lay, gr, reps, nb, status, ok_aos in cases:
+        with pytest.raises(sv.SphvError) as e:
+            sv.autotune_grid(fake if ok_aos else None, dd, df, n, p, sv.PREC_FP64, lay, l, gr, fake, reps=reps,
+                             ws_bytes=nb)
+        assert e.value.status == status
