@@ -7,6 +7,12 @@ one stream.  The workload is the two-state tube: a 64^3 lattice (density 1,
 pressure 1) beside a 32^3 lattice (density 1/8, pressure 0.1) in the periodic
 box [0,2]x[0,1]^2, 294,912 particles in 256-byte records, FP64.
 
+Before the timed runs the library's tuner picks, untimed, each loop's layout
+and tile shape on the same records (with --tune-grid also the grid: cells per
+support length 1, 2 or 3); the timed steps run with that choice (--no-tune:
+SoA views).  The grid is otherwise the generated one, two cells per support of
+the right state's h.
+
 value = (density pairs + force pairs) per second over the timed steps, the pairs
 counted by the kernels themselves (j != i inside the support at the accepted h).
 Prints one JSON line.
@@ -42,10 +48,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_loops_tube64_fp64_counters.m
 PAIR_SRC = os.path.join(ROOT, "paper_2502_16517_amd", "csrc", "k_pair.hip")
 
 
-def measured_traffic():
+def measured_traffic(choice):
     """HBM bytes per launch of the two pair loops, from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or
-    None when that summary was taken on another version of the pair kernels."""
+    None when that summary was taken on another version of the pair kernels or
+    with another grid or layouts than `choice`."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()[:16]
@@ -56,19 +63,59 @@ def measured_traffic():
         if not line.startswith("traffic:"):
             continue
         kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
-        if kv.get("k_pair.hip sha256/16", kv.get("sha256/16")) != src:
+        if kv.get("sha256/16") != src:
+            return None
+        if any(kv.get(k) != v for k, v in choice.items()):
             return None
         return {"density": float(kv["density"]), "force": float(kv["force"])}
     return None
 
 
-def make_stepper(torch, sv, inputs, w, precision, lay):
-    p = sv.params_for(w)
+def make_stepper(torch, sv, inputs, w, precision, tuned=None):
+    """A Stepper on the workload; tuned = (grid, density layout, force layout)."""
+    grid, ld, lf = tuned if tuned else (tuple(w.grid), sv.layout(), sv.layout())
+    p = sv.params_init(w.lo, w.length, grid, w.periodic)
+    p.eta = w.eta
     if precision == sv.PREC_FP32:
         p.h_tol = 1e-6
-    st = sv.Stepper(w.rec, p, precision, layout_density=lay, layout_force=lay,
+    st = sv.Stepper(w.rec, p, precision, layout_density=ld, layout_force=lf,
                     stream=torch.cuda.current_stream())
     return st
+
+
+def tune(torch, sv, inputs, w, precision, tune_grid):
+    """The tuner's choice for this workload: after two steps (valid force
+    inputs), each loop's layout and tile shape over the built-in candidates;
+    with tune_grid first the grid among cells per support 1, 2, 3 of the
+    largest h.  Untimed set-up; the tables go to stderr."""
+    st = make_stepper(torch, sv, inputs, w, precision)
+    for _ in range(2):
+        st.step()
+    cps = None
+    h_ref = None
+    if tune_grid:
+        cps = (1, 2, 3)
+        h_ref = float(st.records()[:, inputs.SLOT["h"]].max())
+    res = st.autotune(reps=3, cells_per_support=cps, h_ref=h_ref)
+    grid = tuple(st.p.grid)
+    ld, lf = st.ld, st.lf
+    st.close()
+    if tune_grid:
+        log(f"[bench]   grid candidates (ms for cells_build + density + force): "
+            + ", ".join(f"{'x'.join(map(str, g))} {ms:.3f}" for g, ms in res["grid"][1])
+            + f" -> {'x'.join(map(str, grid))}")
+    for key in ("density", "force"):
+        best, table = res[key]
+        top = sorted(table, key=lambda t: t[1])[:4]
+        log(f"[bench]   {key}: " + ", ".join(f"{sv.layout_name(l)} {ms:.3f}" for l, ms in top)
+            + f" -> {sv.layout_name(best)}")
+    return grid, ld, lf
+
+
+def choice_of(sv, tuned):
+    grid, ld, lf = tuned
+    return {"grid": "x".join(map(str, grid)), "density_layout": sv.layout_name(ld),
+            "force_layout": sv.layout_name(lf)}
 
 
 def run_timed(torch, sv, st, steps, warmup, graph=False):
@@ -178,6 +225,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the tuner: SoA views for both loops")
+    ap.add_argument("--tune-grid", action="store_true",
+                    help="let the tuner pick the grid too (it times one snapshot of the particles; over the "
+                         "timed steps the generated grid did better on this workload)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic kernel for "
                          "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -207,10 +259,14 @@ def main():
         del src, dst
     log("[bench] generating the two-state tube (294,912 particles)")
     w = inputs.config2()
-    lay = sv.layout(sv.LAYOUT_SOA)
+    if args.no_tune:
+        t64 = (tuple(w.grid), sv.layout(), sv.layout())
+    else:
+        log("[bench] tuning fp64 (untimed)")
+        t64 = tune(torch, sv, inputs, w, sv.PREC_FP64, args.tune_grid)
 
     log("[bench] fp64 eager")
-    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, t64)
     r64 = run_timed(torch, sv, st, args.steps, args.warmup)
     evals_d, pairs_f, pairs_d = pair_evals_per_step(torch, sv, st)
     st.close()
@@ -218,17 +274,23 @@ def main():
         log(f"[bench] warning: status flags {r64['flags']:#x}")
 
     log("[bench] fp64 graph")
-    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, t64)
     g64 = run_timed(torch, sv, st, args.steps, args.warmup, graph=True)
     st.close()
 
     f32 = None
     if not args.no_fp32:
+        if args.no_tune:
+            t32 = (tuple(w.grid), sv.layout(), sv.layout())
+        else:
+            log("[bench] tuning fp32 (untimed)")
+            t32 = tune(torch, sv, inputs, w, sv.PREC_FP32, args.tune_grid)
         log("[bench] fp32 eager")
-        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP32, lay)
+        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP32, t32)
         r32 = run_timed(torch, sv, st, args.steps, args.warmup)
         st.close()
         f32 = {"value": r32["pairs"] / (r32["ms_total"] / 1e3), "ms_per_step": r32["ms_total"] / args.steps,
+               "choice": choice_of(sv, t32),
                "ms_density": r32["ms_density"], "ms_force": r32["ms_force"], "ms_span": r32["ms_span"],
                "speedup_vs_fp64": (r32["pairs"] / r32["ms_total"]) / (r64["pairs"] / r64["ms_total"])}
 
@@ -242,9 +304,11 @@ def main():
     else:
         kern, flops, ms_k = "density", dens_flops, r64["ms_density"]
     achieved = flops / (ms_k / 1e3) / 1e12
-    tr = measured_traffic()
+    choice = choice_of(sv, t64)
+    tr = measured_traffic(choice)
     traffic = tr[kern] if tr else None
-    roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop)", "achieved": achieved,
+    roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop, {choice[kern + '_layout']})",
+                "achieved": achieved,
                 "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VALU / 1e12),
                 "traffic": traffic,
                 "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12},
@@ -269,9 +333,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "two-state tube 64^3 + 32^3 = 294,912 particles, periodic [0,2]x[0,1]^2, "
-                               "256-byte 32-slot records, SoA views, FP64",
-                   "n": w.n, "grid": list(w.grid), "layout": "soa", "tpi": "auto", "pairs_per_step":
-                       {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
+                               "256-byte 32-slot records, FP64",
+                   "n": w.n, "grid": list(t64[0]), "tuned": not args.no_tune,
+                   "layout": {"density": choice["density_layout"], "force": choice["force_layout"]},
+                   "pairs_per_step": {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "graph": {"value": g64["pairs"] / (g64["ms_total"] / 1e3), "ms_per_step": g64["ms_total"] / args.steps},

@@ -246,7 +246,10 @@ enum { SPHV_PREC_FP64 = 0, SPHV_PREC_FP32 = 1 };
  * tpi: lanes that share one local particle (1..64, 0 = automatic: 64 / count
  * of the work item).  masked: 1 evaluates every candidate pair and multiplies
  * out-of-range terms by zero (Sec. 5.6, neutral elements), 0 branches.  Both
- * give bit-identical results; tpi changes the summation order. */
+ * give bit-identical results; tpi changes the summation order.  Either form of
+ * the density loop caches, per work item, which candidates lie within twice
+ * its cell cap; a branching force loop with the same tpi and precision reuses
+ * them instead of testing every candidate again. */
 typedef struct {
     uint32_t kind;
     uint32_t aosoa_width;   /* power of two, 8..1024, for SPHV_LAYOUT_AOSOA */
@@ -342,8 +345,10 @@ int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
  * the gather of A_in, the loop and the scatter of A_out of a view with that
  * layout, over the records aos_dev (described by d, indexed by the cells'
  * perm), starting from the records as they are.  Each candidate runs reps
- * trials; its figure is their median.  The fastest candidate is written to
- * *best and the medians, in candidate order, to ms (NULL: not reported).
+ * trials; its figure is their median.  Medians within 1.5 % of the smallest
+ * count as equal (timing noise): *best is the first such candidate in the
+ * given order, so repeated tuning settles on one choice.  The medians, in
+ * candidate order, go to ms (NULL: not reported).
  *
  * candidates: NULL for the built-in set (sphv_autotune_candidates), else an
  *   array of n_candidates (1..128) layouts.
@@ -351,6 +356,11 @@ int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
  *   trial and copied back after each trial and at the end, so the records
  *   leave the call as they came in.  Run it on records that hold a valid
  *   state for the loop (for the force loop: after a density scatter).
+ * Coupling: the force loop reuses the candidate masks the density loop cached
+ *   in the cells when both ran unmasked with the same tpi.  Force trials read
+ *   the cache as the caller's last density call left it (density trials
+ *   overwrite it with their last unmasked candidate's), so tune the density
+ *   loop first, run it once with the chosen layout, then tune the force loop.
  * SPHV_LAYOUT_SORTED candidates: the trial starts with sphv_records_sort (its
  *   time counts, as the layout needs it) and afterwards moves the records,
  *   the cells' perm and key back to where they were, so cells (const for the
@@ -393,8 +403,8 @@ int32_t sphv_grid_for(const sphv_params* p, double h_ref, int32_t cells_per_supp
  * l_density and l_force (not SPHV_LAYOUT_SORTED: SPHV_E_UNSUPPORTED).  The
  * members of d_density and d_force are restored bit for bit after each trial,
  * as in sphv_autotune; cells_build takes x, y, z, h from d_density.  *best is
- * the index of the grid with the smallest median, ms the medians (NULL: not
- * reported).  The caller then builds its own cells with that grid.  Host
+ * the index of the first grid whose median is within 1.5 % of the smallest,
+ * ms the medians (NULL: not reported).  The caller then builds its own cells with that grid.  Host
  * timing: synchronises stream, SPHV_E_STATE under graph capture. */
 size_t sphv_autotune_grid_workspace_bytes(const sphv_descriptor* d_density, const sphv_descriptor* d_force,
                                           int64_t n, const sphv_params* p, int32_t precision,

@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
     const int n_items = a.meta[META_NITEMS];
     const int xcd = blockIdx.x % kNumXcd;
     const double eta3 = a.eta * a.eta * a.eta;
-    if (!MASKED && blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 1 + a.tpi + (FP32 ? 128 : 0);
+    if (blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 1 + a.tpi + (FP32 ? 128 : 0);
     int qoff = 0;
     unsigned long long n_final = 0, n_evals = 0;
     int maxit = 0;
@@ -679,8 +679,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 __syncthreads();
                 uint64_t hits = 0, caph = 0;
                 if (act) lane_mask2<R>(sx, sy, sz, count, sl, tpi, xi, yi, zi, Hl2w, H2capw, hits, caph);
-                if (!MASKED && c < kMaskChunks)
-                    a.item_masks[((int64_t)item * kMaskChunks + c) * kWave + lane] = caph;
+                if (c < kMaskChunks) a.item_masks[((int64_t)item * kMaskChunks + c) * kWave + lane] = caph;
                 for (uint64_t m = hits; m; m &= m - 1) s_flag[sl + __builtin_ctzll(m) * tpi] = 1;
                 __syncthreads();
                 // compact the chunk's hits (over all particles) into the union
@@ -782,7 +781,10 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                         const R dz = zi - c.z;
                         const R r2 = dx * dx + dy * dy + dz * dz;
                         const bool in = r2 < H2;
-                        if (MASKED || in) term(c.m, r2, in, p0, p1, p2);
+                        // list entries lie within the list radius, so nearly all are in
+                        // range: the neutral-element select costs less than a divergent
+                        // branch, and gives the same bits
+                        term(c.m, r2, in, p0, p1, p2);
                         cnt += (in && u != self_u) ? 1 : 0;
                         if (FP32 && ++k == 16) {
                             fold(p0, p1, p2);
@@ -799,6 +801,16 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                     if (done) return;
                     R p0 = 0, p1 = 0, p2 = 0;
                     if constexpr (MASKED) {
+                        // the force loop's candidates within 2 hcap, cached as in the
+                        // branching form
+                        if (pass == 0 && chunk < kMaskChunks)
+                            a.item_masks[((int64_t)item * kMaskChunks + chunk) * kWave + lane] =
+                                lane_mask(count, sl, tpi, [&](int t) {
+                                    const R dx = xi - sx[t];
+                                    const R dy = yi - sy[t];
+                                    const R dz = zi - sz[t];
+                                    return fma(dz, dz, fma(dy, dy, dx * dx)) < H2capw;
+                                });
                         // every candidate evaluated, out-of-range terms are the neutral element
                         for (int t = sl; t < count; t += tpi) {
                             const R dx = xi - sx[t];

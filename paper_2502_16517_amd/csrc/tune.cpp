@@ -31,6 +31,19 @@ constexpr uint64_t kAlignT = 256;
 constexpr int kMaxCand = 128;
 constexpr int kMaxGrids = 16;
 constexpr double kGridHeadroom = 1.1;   // cell edge over the support it is sized for
+// Candidates whose medians lie within this fraction of the fastest are taken
+// as equal (run-to-run timing noise); the first of them in the caller's order
+// is chosen, so repeated tuning returns the same choice.
+constexpr float kTieMul = 1.015f;
+
+int pick(const std::vector<float>& med)
+{
+    float lo = med[0];
+    for (float m : med) lo = std::min(lo, m);
+    for (size_t k = 0; k < med.size(); ++k)
+        if (med[k] <= lo * kTieMul) return (int)k;
+    return 0;
+}
 
 uint64_t up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -266,8 +279,7 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
     Events ev;
     if (!ev.ok) return SPHV_E_HIP;
     int32_t status = SPHV_OK;
-    float best_ms = 0.f;
-    int best_k = -1;
+    std::vector<float> meds;
     std::vector<float> trial((size_t)reps);
     for (int k = 0; k < n_cand && status == SPHV_OK; ++k) {
         const bool srt = cand[k].kind == SPHV_LAYOUT_SORTED;
@@ -294,15 +306,12 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
         if (status) break;
         const float med = median(trial);
         if (ms_out) ms_out[k] = med;
-        if (best_k < 0 || med < best_ms) {
-            best_ms = med;
-            best_k = k;
-        }
+        meds.push_back(med);
     }
     // the records as they came in, whatever happened above
     if (n > 0 && restore(b, s) != hipSuccess && status == SPHV_OK) status = SPHV_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess && status == SPHV_OK) status = SPHV_E_HIP;
-    if (status == SPHV_OK) *best = cand[best_k];
+    if (status == SPHV_OK) *best = cand[pick(meds)];
     return status;
 }
 
@@ -387,8 +396,7 @@ int32_t sphv_autotune_grid(void* aos, const sphv_descriptor* d_density, const sp
     Events ev;
     if (!ev.ok) return SPHV_E_HIP;
     int32_t status = SPHV_OK;
-    float best_ms = 0.f;
-    int best_g = -1;
+    std::vector<float> meds;
     std::vector<float> trial((size_t)reps);
     for (int g = 0; g < n_grids && status == SPHV_OK; ++g) {
         const sphv_params pg = with_grid(p, grids + 3 * g);
@@ -421,15 +429,12 @@ int32_t sphv_autotune_grid(void* aos, const sphv_descriptor* d_density, const sp
         if (status) break;
         const float med = median(trial);
         if (ms_out) ms_out[g] = med;
-        if (best_g < 0 || med < best_ms) {
-            best_ms = med;
-            best_g = g;
-        }
+        meds.push_back(med);
     }
     if (n > 0 && (restore(bf, s) != hipSuccess || restore(bd, s) != hipSuccess) && status == SPHV_OK)
         status = SPHV_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess && status == SPHV_OK) status = SPHV_E_HIP;
-    if (status == SPHV_OK) *best = best_g;
+    if (status == SPHV_OK) *best = pick(meds);
     return status;
 }
 

@@ -595,7 +595,10 @@ class Stepper:
         both views with them.  With cells_per_support (e.g. (1, 2)) it first
         picks the grid among sphv_grid_for(h_ref, k) for those k, h_ref
         defaulting to the records' largest h, and rebuilds the cells on it.
-        Returns {"density": (best, table), "force": ..., ["grid": ...]}."""
+        The density layout is chosen first; the force layouts are then timed
+        after one density pass with it (the records hold that pass's results
+        afterwards).  Returns {"density": (best, table), "force": ...,
+        ["grid": ...]}."""
         out = {}
         if cells_per_support:
             if h_ref is None:
@@ -625,7 +628,15 @@ class Stepper:
             out[key] = autotune(loop, self.aos, d, self.cells, self.p, self.precision, ws, candidates, reps,
                                 self.stream)
             del ws
-        self.set_layouts(out["density"][0], out["force"][0])
+            if loop == LOOP_DENSITY:
+                # the force loop reuses the density loop's cached candidate masks
+                # when both use the same lanes per particle; the density trials
+                # left the cache of their last candidate, so one density pass
+                # with the chosen layout sets the state a step gives the force loop
+                self.set_layouts(layout_density=out["density"][0])
+                self.build()
+                self.density()
+        self.set_layouts(layout_force=out["force"][0])
         return out
 
     def records(self) -> np.ndarray:

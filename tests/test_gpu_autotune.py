@@ -36,10 +36,11 @@ def test_autotune_leaves_records_and_picks_a_candidate(precision):
         assert np.array_equal(bits(before), bits(after)), loop
         assert len(table) == len(SUBSET)
         assert all(ms > 0 for _, ms in table)
+        # the first candidate within 1.5 % of the fastest (timing noise)
         fastest = min(ms for _, ms in table)
+        first = next(c for c, ms in table if ms <= fastest * np.float32(1.015))
         key = (best.kind, best.aosoa_width, best.tpi, best.masked)
-        picks = [(c.kind, c.aosoa_width, c.tpi, c.masked) for c, ms in table if ms == fastest]
-        assert key in picks
+        assert key == (first.kind, first.aosoa_width, first.tpi, first.masked)
     state = st.read_state()
     assert state.nstep == 1       # the trials used their own state block
     st.close()

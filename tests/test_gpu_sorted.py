@@ -224,7 +224,8 @@ def test_grid_tuner(orc):
                                    ws, reps=2)
     print(table, flush=True)
     assert best in (0, 1) and all(ms > 0 for _, ms in table)
-    assert table[best][1] == min(ms for _, ms in table)
+    fastest = min(ms for _, ms in table)
+    assert best == next(k for k, (_, ms) in enumerate(table) if ms <= fastest * np.float32(1.015))
     assert np.array_equal(bits(st.records()), bits(before))
     # through the Stepper: choose, rebuild on the grid, step, check
     res = st.autotune(candidates=[sv.layout(), sv.layout(tpi=2)], reps=2, cells_per_support=(1, 2), h_ref=h_ref)
