@@ -112,6 +112,14 @@ def tune(torch, sv, inputs, w, precision, tune_grid):
     return grid, ld, lf
 
 
+def layout_of(sv, name):
+    """Inverse of sphview.layout_name: kind/tpiN|tpiauto/branch|masked."""
+    kind, tpi, mode = name.split("/")
+    kinds = {"soa": (sv.LAYOUT_SOA, 0), "direct": (sv.LAYOUT_DIRECT, 0), "sorted": (sv.LAYOUT_SORTED, 0)}
+    k, wdt = kinds[kind] if kind in kinds else (sv.LAYOUT_AOSOA, int(kind[len("aosoa"):]))
+    return sv.layout(k, wdt, tpi=0 if tpi == "tpiauto" else int(tpi[3:]), masked=1 if mode == "masked" else 0)
+
+
 def choice_of(sv, tuned):
     grid, ld, lf = tuned
     return {"grid": "x".join(map(str, grid)), "density_layout": sv.layout_name(ld),
@@ -227,6 +235,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the tuner: SoA views for both loops")
+    ap.add_argument("--layouts", default=None,
+                    help="DENSITY,FORCE layout names as the tuner prints them (e.g. direct/tpiauto/branch,"
+                         "soa/tpiauto/branch): use these instead of tuning (profiling runs)")
     ap.add_argument("--tune-grid", action="store_true",
                     help="let the tuner pick the grid too (it times one snapshot of the particles; over the "
                          "timed steps the generated grid did better on this workload)")
@@ -259,7 +270,10 @@ def main():
         del src, dst
     log("[bench] generating the two-state tube (294,912 particles)")
     w = inputs.config2()
-    if args.no_tune:
+    if args.layouts:
+        names = args.layouts.split(",")
+        t64 = (tuple(w.grid), layout_of(sv, names[0]), layout_of(sv, names[1]))
+    elif args.no_tune:
         t64 = (tuple(w.grid), sv.layout(), sv.layout())
     else:
         log("[bench] tuning fp64 (untimed)")
@@ -334,7 +348,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "two-state tube 64^3 + 32^3 = 294,912 particles, periodic [0,2]x[0,1]^2, "
                                "256-byte 32-slot records, FP64",
-                   "n": w.n, "grid": list(t64[0]), "tuned": not args.no_tune,
+                   "n": w.n, "grid": list(t64[0]), "tuned": not (args.no_tune or args.layouts),
                    "layout": {"density": choice["density_layout"], "force": choice["force_layout"]},
                    "pairs_per_step": {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
         "roofline": roofline,
