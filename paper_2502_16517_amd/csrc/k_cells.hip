@@ -68,18 +68,11 @@ __global__ void k_state_init(DevState* st, int full)
     st->max_iters = 0;
 }
 
-__global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,
-                      uint64_t stride, Geom g, int64_t n, int32_t* key, int32_t* counts,
-                      uint32_t* hmax_bits, DevState* st)
+// Cell key and support bits of one particle; flags non-finite input and
+// particles outside an open box.
+__device__ __forceinline__ void bin_one(const double c[3], double h, const Geom& g, DevState* st, int& kk,
+                                        uint32_t& hbits)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t rb = (uint64_t)i * stride;
-    double c[3];
-    c[0] = *(const double*)(fx.base + fx.off + rb);
-    c[1] = *(const double*)(fy.base + fy.off + rb);
-    c[2] = *(const double*)(fz.base + fz.off + rb);
-    double h = *(const double*)(fh.base + fh.off + rb);
     bool finite = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]);
     int k[3];
     bool outside = false;
@@ -91,20 +84,66 @@ __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, c
         if (t > (double)(g.n[d] - 1)) { t = (double)(g.n[d] - 1); outside = true; }
         k[d] = (int)t;
     }
-    int kk = finite ? cell_key(k[0], k[1], k[2], g) : 0;
-    key[i] = kk;
-    atomicAdd(&counts[kk], 1);
+    kk = finite ? cell_key(k[0], k[1], k[2], g) : 0;
     // support radius with headroom; positive floats order like their bits
     float H = __double2float_ru(2.0 * h * g.headroom);
     if (!(isfinite(h) && h > 0.0)) {
         set_flag(st, SPHV_F_NONFINITE_INPUT);
         H = 0.0f;
     }
-    atomicMax(&hmax_bits[kk], __float_as_uint(H));
+    hbits = __float_as_uint(H);
     if (!finite) set_flag(st, SPHV_F_NONFINITE_INPUT);
     bool open_out = false;
     for (int d = 0; d < 3; ++d) open_out |= (!g.periodic[d] && outside);
     if (finite && open_out) set_flag(st, SPHV_F_OUT_OF_BOX);
+}
+
+__global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,
+                      uint64_t stride, Geom g, int64_t n, int32_t* key, int32_t* counts,
+                      uint32_t* hmax_bits, DevState* st)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t rb = (uint64_t)i * stride;
+    double c[3];
+    c[0] = *(const double*)(fx.base + fx.off + rb);
+    c[1] = *(const double*)(fy.base + fy.off + rb);
+    c[2] = *(const double*)(fz.base + fz.off + rb);
+    const double h = *(const double*)(fh.base + fh.off + rb);
+    int kk;
+    uint32_t hb;
+    bin_one(c, h, g, st, kk, hb);
+    key[i] = kk;
+    atomicAdd(&counts[kk], 1);
+    atomicMax(&hmax_bits[kk], hb);
+}
+
+// k_bin on records staged through LDS; consecutive particles of one cell (a
+// lattice row, say) add to their cell's counters once per run of lanes.
+__global__ __launch_bounds__(kStageThreads) void k_bin_staged(const FieldRef fx, const FieldRef fy, const FieldRef fz,
+                                                              const FieldRef fh, StagePlan sp, uint64_t stride,
+                                                              Geom g, int64_t n, int32_t* key, int32_t* counts,
+                                                              uint32_t* hmax_bits, DevState* st)
+{
+    extern __shared__ uint4 tile[];
+    const int64_t r0 = (int64_t)blockIdx.x * kStageThreads;
+    stage_in(tile, fx.base, stride, nullptr, r0, n, sp);
+    const int64_t i = r0 + threadIdx.x;
+    const bool valid = i < n;
+    int kk = 0;
+    uint32_t hb = 0;
+    if (valid) {
+        const LocTile l{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
+        const double c[3] = {*(const double*)l.at(fx), *(const double*)l.at(fy), *(const double*)l.at(fz)};
+        bin_one(c, *(const double*)l.at(fh), g, st, kk, hb);
+        key[i] = kk;
+    }
+    const int head = run_head(kk, valid);
+    hb = run_max_upto(hb, head);
+    if (run_tail(kk, valid) && valid) {
+        atomicAdd(&counts[kk], (int)(threadIdx.x & (kWave - 1)) - head + 1);
+        atomicMax(&hmax_bits[kk], hb);
+    }
 }
 
 // ---- exclusive scan of int32 (three passes)
@@ -189,12 +228,21 @@ hipError_t scan_excl(const int32_t* in, int64_t m, int32_t* part, int32_t* out, 
     return hipGetLastError();
 }
 
+// Each particle takes a slot of its cell; a run of lanes with one cell takes
+// its slots with one atomic (the order inside a cell is fixed by k_segsort).
 __global__ void k_place(const int32_t* key, int64_t n, int32_t* cursor, int32_t* perm_tmp)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int pos = atomicAdd(&cursor[key[i]], 1);
-    perm_tmp[pos] = (int32_t)i;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int k = valid ? key[i] : 0;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int head = run_head(k, valid);
+    // the run's last lane (lane 63 always ends a run)
+    const int tail = (int)__builtin_ctzll(__ballot(run_tail(k, valid)) & (~0ull << lane));
+    int base = 0;
+    if (valid && lane == tail) base = atomicAdd(&cursor[k], tail - head + 1);
+    base = __shfl(base, tail, kWave);
+    if (valid) perm_tmp[base + lane - head] = (int32_t)i;
 }
 
 constexpr int kSortThreads = 256;
@@ -435,9 +483,17 @@ __global__ void k_force_hbits(const int32_t* perm, const int32_t* key_sorted, Fi
                               int64_t n, uint32_t* hbits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
-    atomicMax(&hbits[key_sorted[p]], __float_as_uint(__double2float_ru(2.0 * v)));
+    const bool valid = p < n;
+    int k = 0;
+    uint32_t b = 0;
+    if (valid) {
+        const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
+        b = __float_as_uint(__double2float_ru(2.0 * v));
+        k = key_sorted[p];
+    }
+    // sorted positions: a cell's particles are consecutive lanes, one atomic per run
+    b = run_max_upto(b, run_head(k, valid));
+    if (valid && run_tail(k, valid)) atomicMax(&hbits[k], b);
 }
 
 constexpr int kOwnThreads = 1024;
@@ -551,8 +607,14 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     if ((e = clear3((uint32_t*)c.counts, c.nc, c.hmax_bits, c.nc, (uint32_t*)c.meta, META_SIZE, s)) != hipSuccess)
         return e;
     if (c.n > 0) {
-        hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride, g,
-                           c.n, c.key, c.counts, c.hmax_bits, st);
+        StagePlan sp;
+        if (!rec.index && plan_stage(f, 4, 0u, rec.stride, &sp))
+            hipLaunchKernelGGL(k_bin_staged, dim3(nblk(c.n, kStageThreads)), dim3(kStageThreads),
+                               kStageThreads * sp.nch * 16, s, f[0], f[1], f[2], f[3], sp, rec.stride, g, c.n, c.key,
+                               c.counts, c.hmax_bits, st);
+        else
+            hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride, g,
+                               c.n, c.key, c.counts, c.hmax_bits, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan_excl(c.counts, c.nc, c.scan_part, c.cell_start, c.cursor, s)) != hipSuccess) return e;

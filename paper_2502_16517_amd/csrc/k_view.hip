@@ -46,6 +46,32 @@ __global__ __launch_bounds__(kConvThreads) void k_gather(FieldPack fp, int nf, A
     }
 }
 
+// k_gather on records staged through LDS (all source members 8 bytes).
+__global__ __launch_bounds__(kStageThreads) void k_gather_staged(FieldPack fp, int nf, StagePlan sp, Access sa,
+                                                                 Access da, const int32_t* cell_key, Geom g,
+                                                                 int64_t n)
+{
+    extern __shared__ uint4 tile[];
+    const int64_t r0 = (int64_t)blockIdx.x * kStageThreads;
+    stage_in(tile, fp.src[0].base, sa.stride, sa.index, r0, n, sp);
+    const int64_t p = r0 + threadIdx.x;
+    if (p >= n) return;
+    const LocTile ls{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
+    Loc<false> ld = locate<false>(da, p);
+    int key = cell_key ? cell_key[sa.index ? sa.index[p] : p] : 0;
+    for (int k = 0; k < nf; ++k) {
+        const FieldRef& s = fp.src[k];
+        const FieldRef& d = fp.dst[k];
+        if (d.size == 8) {
+            *(uint64_t*)ld.at(d) = *(const uint64_t*)ls.at(s);
+        } else {
+            FieldRef q = s;
+            q.rel_axis = d.rel_axis;
+            *(float*)ld.at(d) = ld_as_f32(q, ls, g, key);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kConvThreads) void k_scatter(FieldPack fp, int nf, Access sa, Access da, int64_t n)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,18 +90,12 @@ struct KickFields {
     FieldRef f[15];   // x y z vx vy vz vhx vhy vhz ax ay az u uh u_dt
 };
 
-__global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint64_t stride, Geom g,
-                                                             const DevState* st, int64_t n)
+// The kick / drift / kick update of one record (every product and sum rounded
+// on its own); P(k) addresses member k in the order of KickFields.
+template <class Ptr>
+__device__ __forceinline__ void kick_one(Ptr&& P, const Geom& g, double dt, double half, double half_prev,
+                                         bool first)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double dt = st->dt;
-    const double dt_prev = st->dt_prev;
-    const bool first = st->nstep <= 1;
-    const double half = __dmul_rn(0.5, dt);
-    const double half_prev = __dmul_rn(0.5, dt_prev);
-    uint64_t rb = (uint64_t)i * stride;
-    auto P = [&](int k) -> double* { return (double*)(kf.f[k].base + kf.f[k].off + rb); };
     for (int d = 0; d < 3; ++d) {
         double a = *P(9 + d);
         double v = *P(3 + d);
@@ -97,6 +117,40 @@ __global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint
     double uh = __dadd_rn(u, __dmul_rn(du, half));
     *P(13) = uh;
     *P(12) = __dadd_rn(uh, __dmul_rn(du, half));
+}
+
+__global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint64_t stride, Geom g,
+                                                             const DevState* st, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = st->dt;
+    const uint64_t rb = (uint64_t)i * stride;
+    auto P = [&](int k) -> double* { return (double*)(kf.f[k].base + kf.f[k].off + rb); };
+    kick_one(P, g, dt, __dmul_rn(0.5, dt), __dmul_rn(0.5, st->dt_prev), st->nstep <= 1);
+}
+
+// The kick on records staged through LDS (stage_in / stage_out).
+__global__ __launch_bounds__(kStageThreads) void k_kick_staged(KickFields kf, StagePlan sp, uint64_t stride, Geom g,
+                                                               const DevState* st, int64_t n)
+{
+    extern __shared__ uint4 tile[];   // kStageThreads records x nch chunks
+    const int64_t r0 = (int64_t)blockIdx.x * kStageThreads;
+    char* const base = kf.f[0].base;
+    const int nch = (int)sp.nch;
+    stage_in(tile, base, stride, nullptr, r0, n, sp);
+    const int64_t i = r0 + threadIdx.x;
+    if (i < n) {
+        char* const mine = (char*)&tile[threadIdx.x * nch] - (uint64_t)sp.c0 * 16;
+        auto P = [&](int k) -> double* { return (double*)(mine + kf.f[k].off); };
+        const double dt = st->dt;
+        kick_one(P, g, dt, __dmul_rn(0.5, dt), __dmul_rn(0.5, st->dt_prev), st->nstep <= 1);
+        for (uint32_t m = sp.direct; m; m &= m - 1) {
+            const int k = __builtin_ctz(m);
+            *(double*)(base + kf.f[k].off + (uint64_t)i * stride) = *P(k);
+        }
+    }
+    stage_out(tile, base, stride, nullptr, r0, n, sp);
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kConvThreads - 1) / kConvThreads); }
@@ -171,7 +225,12 @@ hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const
         fp.src[k] = src[k];
         fp.dst[k] = dst[k];
     }
-    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, cell_key, g, n);
+    StagePlan sp;
+    if (n > 0 && nf > 0 && plan_stage(fp.src, nf, 0u, sa.stride, &sp))
+        hipLaunchKernelGGL(k_gather_staged, dim3((unsigned)((n + kStageThreads - 1) / kStageThreads)),
+                           dim3(kStageThreads), kStageThreads * sp.nch * 16, s, fp, nf, sp, sa, da, cell_key, g, n);
+    else
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, cell_key, g, n);
     return hipGetLastError();
 }
 
@@ -192,7 +251,15 @@ hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g
 {
     KickFields kf;
     for (int k = 0; k < 15; ++k) kf.f[k] = f[k];
-    hipLaunchKernelGGL(k_kick_drift, dim3(nblk(n)), dim3(kConvThreads), 0, s, kf, rec.stride, g, st, n);
+    // written: x y z vx vy vz vhx vhy vhz u uh (members 0-8, 12, 13)
+    StagePlan sp;
+    if (n > 0 && !rec.index && plan_stage(kf.f, 15, 0x31FFu, rec.stride, &sp)) {
+        const unsigned blocks = (unsigned)((n + kStageThreads - 1) / kStageThreads);
+        hipLaunchKernelGGL(k_kick_staged, dim3(blocks), dim3(kStageThreads), kStageThreads * sp.nch * 16, s, kf, sp,
+                           rec.stride, g, st, n);
+    } else {
+        hipLaunchKernelGGL(k_kick_drift, dim3(nblk(n)), dim3(kConvThreads), 0, s, kf, rec.stride, g, st, n);
+    }
     return hipGetLastError();
 }
 
