@@ -12,7 +12,7 @@ namespace sphv {
 constexpr int kMaxFields = 32;
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, one L2 each
-constexpr int kRedBlock = 1024;  // particles per block of the fixed-order reductions
+constexpr int kRedBlock = 256;   // particles per block of the fixed-order reductions
 constexpr int kMaskChunks = 12;  // candidate chunks per work item whose hit masks are cached
 constexpr int kQStride = 1024;   // ints between two queue heads: one 4 KiB page each, so that their
                                  // atomics do not queue up at one memory channel

@@ -1322,6 +1322,57 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(RedArgs r)
     if (threadIdx.x < 9) r.part[(int64_t)blockIdx.x * 16 + threadIdx.x] = lds[threadIdx.x][0];
 }
 
+// k_reduce_part with the records' members staged through LDS: the block's
+// kRedBlock particles in rounds of kStageThreads, thread t taking particles
+// base + t, base + t + kStageThreads, ...; then the same tree as above.
+template <bool DIRECT_OUT>
+__global__ __launch_bounds__(kStageThreads) void k_reduce_staged(RedArgs r, StagePlan sp)
+{
+    extern __shared__ uint4 tile[];
+    __shared__ double lds[9][kStageThreads];
+    const int64_t base = (int64_t)blockIdx.x * kRedBlock;
+    double s[9];
+    for (int k = 0; k < 8; ++k) s[k] = 0.0;
+    s[8] = INFINITY;                          // min h / v_sig
+    for (int round = 0; round < kRedBlock / kStageThreads; ++round) {
+        const int64_t r0 = base + (int64_t)round * kStageThreads;
+        if (r0 >= r.n) break;                 // the same for the whole block
+        stage_in(tile, r.in[0].base, r.rec.stride, r.rec.index, r0, r.n, sp);
+        const int64_t p = r0 + threadIdx.x;
+        if (p < r.n) {
+            const LocTile lr{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
+            const Loc<DIRECT_OUT> lo = locate<DIRECT_OUT>(r.outacc, p);
+            const double m = ld_f64(r.in[0], lr);
+            const double vx = ld_f64(r.in[1], lr), vy = ld_f64(r.in[2], lr), vz = ld_f64(r.in[3], lr);
+            const double u = ld_f64(r.in[4], lr), h = ld_f64(r.in[5], lr);
+            const double ax = ld_f64(r.out[0], lo), ay = ld_f64(r.out[1], lo), az = ld_f64(r.out[2], lo);
+            const double du = ld_f64(r.out[3], lo), vs = ld_f64(r.out[4], lo);
+            s[0] += m * vx;
+            s[1] += m * vy;
+            s[2] += m * vz;
+            s[3] += m * (0.5 * (vx * vx + vy * vy + vz * vz) + u);
+            s[4] += m * ax;
+            s[5] += m * ay;
+            s[6] += m * az;
+            s[7] += m * (vx * ax + vy * ay + vz * az + du);
+            const double q = h / vs;
+            s[8] = q < s[8] ? q : s[8];
+        }
+        __syncthreads();                      // the tile is reloaded next round
+    }
+    for (int k = 0; k < 9; ++k) lds[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = kStageThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 8; ++k) lds[k][threadIdx.x] += lds[k][threadIdx.x + w];
+            const double o = lds[8][threadIdx.x + w];
+            lds[8][threadIdx.x] = o < lds[8][threadIdx.x] ? o : lds[8][threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) r.part[(int64_t)blockIdx.x * 16 + threadIdx.x] = lds[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_reduce_final(RedArgs r, int64_t nb)
 {
     __shared__ double lds[9][kRedThreads];
@@ -1508,10 +1559,18 @@ hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const Fie
     r.cfl = cfl;
     int64_t nb = (n + kRedBlock - 1) / kRedBlock;
     if (nb < 1) nb = 1;
-    if (out_direct)
+    StagePlan sp;
+    if (n > 0 && plan_stage(r.in, 6, 0u, r.rec.stride, &sp)) {
+        const size_t lds = kStageThreads * sp.nch * 16;
+        if (out_direct)
+            hipLaunchKernelGGL(k_reduce_staged<true>, dim3((unsigned)nb), dim3(kStageThreads), lds, s, r, sp);
+        else
+            hipLaunchKernelGGL(k_reduce_staged<false>, dim3((unsigned)nb), dim3(kStageThreads), lds, s, r, sp);
+    } else if (out_direct) {
         hipLaunchKernelGGL(k_reduce_part<true>, dim3((unsigned)nb), dim3(kRedThreads), 0, s, r);
-    else
+    } else {
         hipLaunchKernelGGL(k_reduce_part<false>, dim3((unsigned)nb), dim3(kRedThreads), 0, s, r);
+    }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, r, nb);
     return hipGetLastError();
 }

@@ -46,6 +46,24 @@ __global__ __launch_bounds__(kConvThreads) void k_gather(FieldPack fp, int nf, A
     }
 }
 
+// Scatter with one lane per (element, member): the lanes of a wave store the
+// written members of a few records side by side, so a store instruction
+// touches a few cache lines of those records instead of one line per lane.
+__global__ __launch_bounds__(kConvThreads) void k_scatter_lanes(FieldPack fp, int nf, Access sa, Access da,
+                                                                int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * nf) return;
+    const int64_t p = q / nf;
+    const int k = (int)(q - p * nf);
+    const Loc<false> ls = locate<false>(sa, p);
+    const Loc<true> ld = locate<true>(da, p);
+    const FieldRef s = fp.src[k];
+    const FieldRef d = fp.dst[k];
+    if (d.size == 8) *(uint64_t*)ld.at(d) = *(const uint64_t*)ls.at(s);
+    else *(uint32_t*)ld.at(d) = *(const uint32_t*)ls.at(s);
+}
+
 // k_gather on records staged through LDS (all source members 8 bytes).
 __global__ __launch_bounds__(kStageThreads) void k_gather_staged(FieldPack fp, int nf, StagePlan sp, Access sa,
                                                                  Access da, const int32_t* cell_key, Geom g,
@@ -242,7 +260,10 @@ hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, cons
         fp.src[k] = src[k];
         fp.dst[k] = dst[k];
     }
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, n);
+    if (nf > 1)
+        hipLaunchKernelGGL(k_scatter_lanes, dim3(nblk(n * nf)), dim3(kConvThreads), 0, s, fp, nf, sa, da, n);
+    else
+        hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(kConvThreads), 0, s, fp, nf, sa, da, n);
     return hipGetLastError();
 }
 
