@@ -165,22 +165,9 @@ __device__ int block_scan_excl(int v, int* lds, int& total)
     return excl;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, int64_t m, int32_t* part)
+// exclusive scan of the block totals part[0..nb) in place; part[nb] = grand total
+__device__ void scan_parts(int32_t* part, int64_t nb, int* lds)
 {
-    __shared__ int lds[kScanThreads];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int s = 0;
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < m) s += in[base + k];
-    int total;
-    block_scan_excl(s, lds, total);
-    if (threadIdx.x == 0) part[blockIdx.x] = total;
-}
-
-// single block: exclusive scan of the block totals; part[nb] = grand total
-__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* part, int64_t nb)
-{
-    __shared__ int lds[kScanThreads];
     int carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
         int64_t b = b0 + threadIdx.x;
@@ -192,6 +179,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* part, int6
         __syncthreads();
     }
     if (threadIdx.x == 0) part[nb] = carry;
+}
+
+// Block totals; the block that finishes last (ticket nb - 1 on a counter that
+// cells_build zeroes) then scans them, so no separate launch is needed.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, int64_t m, int32_t* part,
+                                                              int32_t* ticket)
+{
+    __shared__ int lds[kScanThreads];
+    __shared__ int last;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += in[base + k];
+    int total;
+    block_scan_excl(s, lds, total);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = total;
+        __threadfence();                  // the total is visible before the ticket is taken
+        last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();                      // every other block's total is visible from here
+    scan_parts(part, gridDim.x, lds);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int64_t m, const int32_t* part,
@@ -218,12 +229,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, 
     if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = part[nb];
 }
 
-hipError_t scan_excl(const int32_t* in, int64_t m, int32_t* part, int32_t* out, int32_t* out2, hipStream_t s)
+// ticket: a zeroed counter of its own for each scan between two zeroings
+hipError_t scan_excl(const int32_t* in, int64_t m, int32_t* part, int32_t* out, int32_t* out2, int32_t* ticket,
+                     hipStream_t s)
 {
     int64_t nb = (m + kScanTile - 1) / kScanTile;
     if (nb == 0) nb = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, m, part);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, m, part, ticket);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, m, part, out, out2);
     return hipGetLastError();
 }
@@ -617,7 +629,8 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
                                c.n, c.key, c.counts, c.hmax_bits, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = scan_excl(c.counts, c.nc, c.scan_part, c.cell_start, c.cursor, s)) != hipSuccess) return e;
+    if ((e = scan_excl(c.counts, c.nc, c.scan_part, c.cell_start, c.cursor, c.meta + META_SCAN, s)) != hipSuccess)
+        return e;
     if (c.n > 0) {
         hipLaunchKernelGGL(k_place, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.key, c.n, c.cursor, c.perm_tmp);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -629,7 +642,8 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];
     hipLaunchKernelGGL(k_row_groups, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, c.tmp_a,
                        c.tmp_b);
-    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, s)) != hipSuccess) return e;
+    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, c.meta + META_SCAN + 1, s)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.tmp_b, c.nc,
                        c.max_items, c.items, c.meta, st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
