@@ -188,7 +188,9 @@ int32_t sphv_write_state(void* state_dev, const sphv_state* in, void* stream);
  * its h is capped at R * min(cell) / 2.  The force loop (sphv_sph_force) sets
  * its own window from the converged h: R_f(c) is the largest of ceil(2 h_max(c)
  * / min cell) and the Chebyshev distance of every cell whose own such reach
- * covers c.  Work items are (cell, first sorted position, count<=64). */
+ * covers c, h_max(c) being the largest h of c seen by the force calls since
+ * the last sphv_cells_build (so repeated force calls never narrow a window).
+ * Work items are (cell, first sorted position, count<=64). */
 typedef struct sphv_cells sphv_cells;
 
 typedef struct {

@@ -251,7 +251,8 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
     c->cell_start = (int32_t*)take(4 * (uint64_t)(nc + 1));
     c->counts = (int32_t*)take(4 * (uint64_t)nc);
     c->cursor = (int32_t*)take(4 * (uint64_t)nc);
-    c->hmax_bits = (uint32_t*)take(4 * (uint64_t)nc);
+    c->hmax_bits = (uint32_t*)take(4 * (uint64_t)nc * 2);
+    c->hmax_f = c->hmax_bits ? c->hmax_bits + nc : nullptr;
     c->reach_d = (int32_t*)take(4 * (uint64_t)nc * 3);
     c->reach_f = c->reach_d ? c->reach_d + nc : nullptr;
     c->reach_s = c->reach_d ? c->reach_d + 2 * nc : nullptr;

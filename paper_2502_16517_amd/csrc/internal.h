@@ -74,6 +74,8 @@ struct CellsDev {
     int32_t* counts;       // [nc]
     int32_t* cursor;       // [nc]
     uint32_t* hmax_bits;   // [nc] float bits of the largest 2 h (times the headroom for the density reach)
+    uint32_t* hmax_f;      // [nc] float bits of the largest 2 h the force loops saw since cells_build
+                           // (directly after hmax_bits: one clear covers both)
     int32_t* reach_d;      // [nc] density reach (cells_build, from h before the density loop)
     int32_t* reach_f;      // [nc] force window radius (sph_force, from the converged h)
     int32_t* reach_s;      // [nc] upper bound of the neighbours' own force reach (box maximum)

@@ -342,8 +342,8 @@ constexpr int kRowMax = 1024;   // rows up to this length are staged in LDS and 
 // lane 0 then walks the row.  For every cell c it leaves gx[c], the cells
 // covered by the items that start at c (0 inside a run), and nit[c], the number
 // of those items; k_items writes them at the exclusive scan of nit.
-__global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start, const int32_t* reach_d, Geom g,
-                                                      int32_t* nit, int32_t* gxo)
+__global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start, const int32_t* counts,
+                                                      const int32_t* reach_d, Geom g, int32_t* nit, int32_t* gxo)
 {
     __shared__ int scnt[kRowMax], srch[kRowMax], scol[kRowMax];
     __shared__ uint8_t sok[kRowMax];
@@ -355,27 +355,36 @@ __global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start,
     const bool staged = nx <= kRowMax;
     if (staged) {
         for (int x = lane; x < nx; x += kWave) {
-            scnt[x] = cell_start[base + x + 1] - cell_start[base + x];
+            scnt[x] = counts[base + x];
             srch[x] = reach_d[base + x];
-            // densest cell of column x over the rows within +-kGroupReach in y and z
-            int m = 0;
+            // densest cell of column x over the rows within +-kGroupReach in y
+            // and z: all 25 loads issued before any is used
+            int rows[2 * kGroupReach + 1][2 * kGroupReach + 1];
+#pragma unroll
             for (int dz = -kGroupReach; dz <= kGroupReach; ++dz) {
-                int z = kz + dz;
-                if (z < 0 || z >= nz) {
-                    if (!g.periodic[2]) continue;
-                    z = z < 0 ? z + nz : z - nz;
-                }
+#pragma unroll
                 for (int dy = -kGroupReach; dy <= kGroupReach; ++dy) {
-                    int y = ky + dy;
+                    int z = kz + dz, y = ky + dy;
+                    bool in = true;
+                    if (z < 0 || z >= nz) {
+                        in = in && g.periodic[2];
+                        z = z < 0 ? z + nz : z - nz;
+                    }
                     if (y < 0 || y >= ny) {
-                        if (!g.periodic[1]) continue;
+                        in = in && g.periodic[1];
                         y = y < 0 ? y + ny : y - ny;
                     }
-                    const int64_t c = ((int64_t)z * ny + y) * nx + x;
-                    const int v = cell_start[c + 1] - cell_start[c];
-                    m = v > m ? v : m;
+                    // a wrapped index of a short periodic axis may still be out of
+                    // range (n < 2 kGroupReach + 1): such a row is skipped
+                    in = in && z >= 0 && z < nz && y >= 0 && y < ny;
+                    rows[dz + kGroupReach][dy + kGroupReach] = in ? counts[((int64_t)z * ny + y) * nx + x] : 0;
                 }
             }
+            int m = 0;
+#pragma unroll
+            for (int a = 0; a < 2 * kGroupReach + 1; ++a)
+#pragma unroll
+                for (int b = 0; b < 2 * kGroupReach + 1; ++b) m = rows[a][b] > m ? rows[a][b] : m;
             scol[x] = m;
         }
         __syncthreads();
@@ -616,7 +625,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
                               hipStream_t s)
 {
     hipError_t e;
-    if ((e = clear3((uint32_t*)c.counts, c.nc, c.hmax_bits, c.nc, (uint32_t*)c.meta, META_SIZE, s)) != hipSuccess)
+    if ((e = clear3((uint32_t*)c.counts, c.nc, c.hmax_bits, 2 * c.nc, (uint32_t*)c.meta, META_SIZE, s)) != hipSuccess)
         return e;
     if (c.n > 0) {
         StagePlan sp;
@@ -640,8 +649,8 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
                        c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];
-    hipLaunchKernelGGL(k_row_groups, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.reach_d, g, c.tmp_a,
-                       c.tmp_b);
+    hipLaunchKernelGGL(k_row_groups, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.counts, c.reach_d, g,
+                       c.tmp_a, c.tmp_b);
     if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, c.meta + META_SCAN + 1, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.tmp_b, c.nc,
@@ -653,15 +662,15 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
 hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Geom& g, DevState* st,
                               hipStream_t s)
 {
+    // hmax_f and the largest own reach start at zero with cells_build and only
+    // grow: a later force call on larger h widens the windows, never narrows them
     hipError_t e;
-    if ((e = clear3((uint32_t*)(c.meta + META_RGLOBAL_F), 1, c.hmax_bits, c.nc, nullptr, 0, s)) != hipSuccess)
-        return e;
     if (c.n > 0) {
         hipLaunchKernelGGL(k_force_hbits, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h, stride, c.n,
-                           c.hmax_bits);
+                           c.hmax_f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_bits,
+    hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_f,
                        g.cmin, c.tmp_a, c.meta, (int)META_RGLOBAL_F, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // separable box maximum over +-R_global (tmp_a -> tmp_b -> reach_f -> reach_s), then the exact window
