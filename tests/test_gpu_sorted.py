@@ -253,3 +253,73 @@ def test_coarse_grid_matches_oracle(orc):
     st.force()
     check_force(st.records(), oracle_force(orc, w, dens), tol=1e-12, vsig_tol=1e-14)
     st.close()
+
+
+def _steps_by_hand(aos, stride, n, p, steps):
+    """cells_build, density and force views (SoA), reduction and kick_drift
+    through the C ABI on records of any stride at any 8-byte aligned base."""
+    u8 = dict(dtype=torch.uint8, device="cuda")
+    fields = lambda spec: [(name, inputs.SLOT[name] * 8, sv.F64, acc) for name, acc in spec]
+    dc, dd, df, dk = (sv.descriptor(fields(s), stride=stride) for s in
+                      (sv.CELLS_FIELDS, sv.DENSITY_FIELDS, sv.FORCE_FIELDS, sv.KICK_FIELDS))
+    state = torch.zeros(sv.state_bytes(), **u8)
+    sv.state_init(state)
+    cws = torch.empty(sv.cells_workspace_bytes(n, p), **u8)
+    cells = sv.cells_create(n, p, cws)
+    perm = sv.cells_get_info(cells).perm
+    lay = sv.layout()
+    views = []
+    for d in (dd, df):
+        ws = torch.empty(sv.view_workspace_bytes(d, n, lay, sv.PREC_FP64), **u8)
+        views.append((sv.view_create(d, n, lay, sv.PREC_FP64, aos, perm, ws), ws))
+    (vd, _), (vf, _) = views
+    for _ in range(steps):
+        sv.begin_step(state)
+        sv.cells_build(cells, aos, dc, state)
+        sv.aos_to_soa(vd, cells)
+        sv.sph_density(vd, cells, p, state)
+        sv.soa_to_aos(vd)
+        sv.aos_to_soa(vf, cells)
+        sv.sph_force(vf, cells, p, state)
+        sv.step_reduce(vf, p, state)
+        sv.soa_to_aos(vf)
+        sv.kick_drift(aos, dk, n, p, state)
+    st = sv.read_state(state)
+    for v, _ in views:
+        sv.view_destroy(v)
+    sv.cells_destroy(cells)
+    return st
+
+
+def test_any_stride_and_alignment_bit_identical(orc):
+    """Records whose stride (264 B) or base (8 B past a 16-B boundary) rule out
+    the LDS staging of the conversions, kick and binning run the plain kernels:
+    the same bits as the staged ones on 256-B records."""
+    w = inputs.two_state_tube(16, 40)
+    n = w.n
+    p = sv.params_for(w)
+    st = sv.Stepper(w.rec, p)
+    for _ in range(2):
+        st.step()
+    ref, sref = st.records(), st.read_state()
+    st.close()
+    # stride 264: one extra slot holding a marker after every record
+    wide = np.zeros((n, 33))
+    wide[:, :32] = w.rec
+    wide[:, 32] = np.arange(n) + 0.5
+    buf = torch.from_numpy(wide.reshape(-1).view(np.uint8).copy()).cuda()
+    s264 = _steps_by_hand(buf, 264, n, p, 2)
+    got = buf.cpu().numpy().view(np.float64).reshape(n, 33)
+    assert np.array_equal(bits(np.ascontiguousarray(got[:, :32])), bits(ref))
+    assert np.array_equal(got[:, 32], np.arange(n) + 0.5)
+    # stride 256 at a base 8 bytes past a 16-byte boundary
+    raw = torch.zeros(n * 256 + 16, dtype=torch.uint8, device="cuda")
+    aos = raw[8:8 + n * 256]
+    assert aos.data_ptr() % 16 == 8
+    aos.copy_(torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(w.rec)).copy()).cuda())
+    s8 = _steps_by_hand(aos, 256, n, p, 2)
+    got8 = aos.cpu().numpy().view(np.float64).reshape(n, 32)
+    assert np.array_equal(bits(got8), bits(ref))
+    for s in (s264, s8):
+        assert s.flags == sref.flags and s.nstep == 2
+        assert s.dt == sref.dt and tuple(s.sums) == tuple(sref.sums)
