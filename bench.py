@@ -140,7 +140,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         g = sv.graph_end(s)
         torch.cuda.synchronize()
     before = st.read_state()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(9)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -157,14 +157,17 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         sv.sph_density(st.v_dens, st.cells, st.p, st.state, s)
         ev[k][1].record(s)
         sv.soa_to_aos(st.v_dens, s)
+        ev[k][6].record(s)
         sv.aos_to_soa(st.v_force, st.cells, s)
         ev[k][2].record(s)
         sv.sph_force(st.v_force, st.cells, st.p, st.state, s)
         ev[k][3].record(s)
         sv.step_reduce(st.v_force, st.p, st.state, s)
+        ev[k][7].record(s)
         sv.soa_to_aos(st.v_force, s)
         ev[k][5].record(s)
         sv.kick_drift(st.aos, st.d_kick, st.n, st.p, st.state, s)
+        ev[k][8].record(s)
     e_end.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -177,6 +180,10 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         res["ms_force"] = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
         # the span of the two views: first density gather to last force scatter
         res["ms_span"] = sum(e[4].elapsed_time(e[5]) for e in ev) / steps
+        # the conversions and the linear kernels, each between its own events
+        for name, a, b in (("density_gather", 4, 0), ("density_scatter", 1, 6), ("force_gather", 6, 2),
+                           ("reduce", 3, 7), ("force_scatter", 7, 5), ("kick_drift", 5, 8)):
+            res["ms_" + name] = sum(e[a].elapsed_time(e[b]) for e in ev) / steps
         log("[bench]   per-step density ms " + " ".join(f"{e[0].elapsed_time(e[1]):.3f}" for e in ev))
         log("[bench]   per-step force ms   " + " ".join(f"{e[2].elapsed_time(e[3]):.3f}" for e in ev))
     if g is not None:
@@ -328,6 +335,21 @@ def main():
                 "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12},
                 "force": {"ms": r64["ms_force"], "tflops": force_flops / (r64["ms_force"] / 1e3) / 1e12}}
 
+    # conversions (the paper's prologue and epilogue) and kick_drift: algorithmic
+    # bytes (members read + members written, per particle) over their event times
+    n = w.n
+    fp64_view = {"density_gather": 40 + 40, "density_scatter": 32 + 32, "force_gather": 96 + 96,
+                 "force_scatter": 40 + 40, "kick_drift": 120 + 88}
+    conv = {}
+    for name, per in fp64_view.items():
+        direct = (name.startswith("density") and t64[1].kind in (sv.LAYOUT_DIRECT, sv.LAYOUT_SORTED)) or \
+                 (name.startswith("force") and t64[2].kind in (sv.LAYOUT_DIRECT, sv.LAYOUT_SORTED))
+        ms = r64["ms_" + name]
+        conv[name] = {"ms": ms, "bytes": 0 if direct and name != "kick_drift" else per * n,
+                      "GB/s": None if direct and name != "kick_drift" else per * n / (ms / 1e3) / 1e9}
+        if conv[name]["GB/s"] is not None:
+            conv[name]["hbm_frac"] = conv[name]["GB/s"] * 1e9 / HBM_PEAK
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -358,11 +380,11 @@ def main():
         # without cells_build and kick_drift
         "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
+        "conversions": conv,
         "hbm_frac_step": None,
     }
     # whole-step HBM fraction: algorithmic view bytes (gathers, scatters, loop
     # inputs and outputs) over the step time
-    n = w.n
     algo_bytes = n * (80 + 64 + 192 + 80) + n * (40 + 32) * max(1, round(evals_d / max(pairs_d, 1))) + n * (96 + 40)
     out["hbm_frac_step"] = algo_bytes / (ms_step / 1e3) / HBM_PEAK
     print(json.dumps(out), flush=True)

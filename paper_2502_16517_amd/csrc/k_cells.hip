@@ -261,8 +261,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
 
-// One wave per cell (grid-stride): order the cell's record indices ascending,
-// which, since the indices are distinct, is the stable order of the sort.
+// One wave per pair of cells (grid-stride): order each cell's record indices
+// ascending, which, since the indices are distinct, is the stable order of the
+// sort.  Two cells of at most 32 particles are sorted side by side, one per
+// half-wave; otherwise the cells are sorted one after the other.
 __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_start, const int32_t* perm_tmp,
                                                           int32_t* perm, int32_t* key_sorted,
                                                           const uint32_t* hmax_bits, int32_t* reach_d,
@@ -274,9 +276,16 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
     int* buf = lds[w];
     int64_t wave_id = (int64_t)blockIdx.x * kSortWaves + w;
     int64_t nwaves = (int64_t)gridDim.x * kSortWaves;
-    for (int64_t c = wave_id; c < nc; c += nwaves) {
-        int b = cell_start[c], e = cell_start[c + 1];
-        int cnt = e - b;
+    auto reach_of = [&](int64_t c, int cnt) {
+        int R = 0;
+        if (cnt > 0) {
+            float H = __uint_as_float(hmax_bits[c]);
+            R = (int)ceil((double)H / g.cmin);
+            if (R < 1) R = 1;
+        }
+        reach_d[c] = R;
+    };
+    auto sort_cell = [&](int64_t c, int b, int cnt) {
         if (cnt <= kWave) {
             int v = lane < cnt ? perm_tmp[b + lane] : 0x7fffffff;
             int rank = 0;
@@ -310,14 +319,32 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
                 key_sorted[b + k] = (int32_t)c;
             }
         }
-        if (lane == 0) {
-            int R = 0;
-            if (cnt > 0) {
-                float H = __uint_as_float(hmax_bits[c]);
-                R = (int)ceil((double)H / g.cmin);
-                if (R < 1) R = 1;
+        if (lane == 0) reach_of(c, cnt);
+    };
+    for (int64_t pr = wave_id; 2 * pr < nc; pr += nwaves) {
+        const int64_t c0 = 2 * pr;
+        const bool two = c0 + 1 < nc;
+        const int b0 = cell_start[c0], b1 = cell_start[c0 + 1];
+        const int e1 = two ? cell_start[c0 + 2] : b1;
+        const int cnt0 = b1 - b0, cnt1 = e1 - b1;
+        if (two && cnt0 <= kWave / 2 && cnt1 <= kWave / 2) {
+            const int half = lane >> 5, hl = lane & 31;
+            const int b = half ? b1 : b0, cnt = half ? cnt1 : cnt0;
+            const int v = hl < cnt ? perm_tmp[b + hl] : 0x7fffffff;
+            const int kmax = cnt0 > cnt1 ? cnt0 : cnt1;
+            int rank = 0;
+            for (int k = 0; k < kmax; ++k) {
+                const int u = __shfl(v, (half << 5) + k, kWave);
+                rank += (k < cnt && u < v) ? 1 : 0;
             }
-            reach_d[c] = R;
+            if (hl < cnt) {
+                perm[b + rank] = v;
+                key_sorted[b + hl] = (int32_t)(c0 + half);
+            }
+            if (hl == 0) reach_of(c0 + half, cnt);
+        } else {
+            sort_cell(c0, b0, cnt0);
+            if (two) sort_cell(c0 + 1, b1, cnt1);
         }
     }
 }
@@ -644,7 +671,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
         hipLaunchKernelGGL(k_place, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.key, c.n, c.cursor, c.perm_tmp);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    unsigned sb = (unsigned)std::min<int64_t>((c.nc + kSortWaves - 1) / kSortWaves, 8192);
+    unsigned sb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((c.nc + 1) / 2 + kSortWaves - 1) / kSortWaves, 8192));
     hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
                        c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
