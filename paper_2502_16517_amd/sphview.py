@@ -595,6 +595,8 @@ class Stepper:
         both views with them.  With cells_per_support (e.g. (1, 2)) it first
         picks the grid among sphv_grid_for(h_ref, k) for those k, h_ref
         defaulting to the records' largest h, and rebuilds the cells on it.
+        candidates: None (the built-in set), a list for both loops, or a dict
+        with a list per loop ("density", "force"); earlier candidates win ties.
         The density layout is chosen first; the force layouts are then timed
         after one density pass with it (the records hold that pass's results
         afterwards).  Returns {"density": (best, table), "force": ...,
@@ -623,9 +625,10 @@ class Stepper:
                 self.set_grid(grids[best])
         self.build()
         for loop, d, key in ((LOOP_DENSITY, self.d_dens, "density"), (LOOP_FORCE, self.d_force, "force")):
-            nb = autotune_workspace_bytes(d, self.n, self.precision, candidates)
+            cands = candidates.get(key) if isinstance(candidates, dict) else candidates
+            nb = autotune_workspace_bytes(d, self.n, self.precision, cands)
             ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)
-            out[key] = autotune(loop, self.aos, d, self.cells, self.p, self.precision, ws, candidates, reps,
+            out[key] = autotune(loop, self.aos, d, self.cells, self.p, self.precision, ws, cands, reps,
                                 self.stream)
             del ws
             if loop == LOOP_DENSITY:
