@@ -127,6 +127,15 @@ def tune(torch, sv, inputs, w, precision, tune_grid):
     res = st.autotune(candidates=cands, reps=3, cells_per_support=cps, h_ref=h_ref)
     grid = tuple(st.p.grid)
     ld, lf = st.ld, st.lf
+    if cands:
+        # between one bench run and the next the trial medians move by a few
+        # per cent: the profiled layouts stay when within 3 % of the fastest
+        pick = {}
+        for key in ("density", "force"):
+            table = res[key][1]
+            lo = min(ms for _, ms in table)
+            pick[key] = next(c for c, ms in table if ms <= 1.03 * lo)
+        ld, lf = pick["density"], pick["force"]
     st.close()
     if tune_grid:
         log(f"[bench]   grid candidates (ms for cells_build + density + force): "
@@ -226,11 +235,11 @@ def pair_evals_per_step(torch, sv, st):
     return s.pair_evals_density, s.pairs_force, s.pairs_density
 
 
-def cpu_baseline(inputs, w):
+def cpu_baseline(inputs, w, reps=3):
     """The oracle (plain scalar C, OpenMP over its target particles, all host
     threads) on one step of the same workload: density with the h iteration
     for every particle, then the force for every particle from the oracle's own
-    density.  On this workload that is about 10 s of CPU work."""
+    density, `reps` times (about 15 thread-seconds of CPU work on 16 cores)."""
     import numpy as np
 
     from oracle import oracle as orc
@@ -240,12 +249,16 @@ def cpu_baseline(inputs, w):
     box = orc.box_of(w.lo, w.length, w.periodic)
     c = {k: np.ascontiguousarray(rec[:, S[k]]) for k in S if k not in inputs.INT_SLOTS}
     nthreads = orc.max_threads()
-    t0 = time.perf_counter()
-    d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads)
-    t1 = time.perf_counter()
-    f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], d["h"], d["rho"], d["omega"],
-                  c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads)
-    t2 = time.perf_counter()
+    td = tf = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads)
+        t1 = time.perf_counter()
+        f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], d["h"], d["rho"], d["omega"],
+                      c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads)
+        t2 = time.perf_counter()
+        td += t1 - t0
+        tf += t2 - t1
     pairs = int(d["count"].sum()) + int(f["count"].sum())
     cpu = platform.processor() or platform.machine()
     try:
@@ -255,9 +268,9 @@ def cpu_baseline(inputs, w):
                 break
     except OSError:
         pass
-    return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"one full step of the same {w.n}-particle workload (density with h iteration "
-                      f"{t1 - t0:.2f} s + force {t2 - t1:.2f} s wall, {nthreads} threads, {cpu})",
+    return {"value": reps * pairs / (td + tf), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{reps} full steps of the same {w.n}-particle workload (per step: density with h "
+                      f"iteration {td / reps:.2f} s + force {tf / reps:.2f} s wall, {nthreads} threads, {cpu})",
             "pairs": pairs}
 
 
