@@ -65,27 +65,38 @@ def profiled_choice():
     return None
 
 
+def kernel_variant(layout_name):
+    """The pair kernel a layout runs: on the records (direct or sorted) or on a
+    view, masked or branching (the FP64 kernels' template arguments)."""
+    kind, _, mode = layout_name.split("/")
+    return ("records" if kind in ("direct", "sorted") else "view", mode)
+
+
 def measured_traffic(choice):
-    """HBM bytes per launch of the two pair loops, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or
-    None when that summary was taken on another version of the pair kernels or
-    with another grid or layouts than `choice`."""
+    """HBM bytes per launch of each pair loop from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), for
+    the loops whose kernel (source hash, grid, records or view, masked or
+    branching) is the one the counters were taken on; with the layout they
+    were taken with.  {} when none applies."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()[:16]
     except OSError:
-        return None
+        return {}
     for line in text.splitlines():
         line = line.strip()
         if not line.startswith("traffic:"):
             continue
         kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
-        if kv.get("sha256/16") != src:
-            return None
-        if any(kv.get(k) != v for k, v in choice.items()):
-            return None
-        return {"density": float(kv["density"]), "force": float(kv["force"])}
-    return None
+        if kv.get("sha256/16") != src or kv.get("grid") != choice["grid"]:
+            return {}
+        out = {}
+        for loop in ("density", "force"):
+            prof = kv.get(loop + "_layout")
+            if prof and kernel_variant(prof) == kernel_variant(choice[loop + "_layout"]):
+                out[loop] = (float(kv[loop]), prof)
+        return out
+    return {}
 
 
 def make_stepper(torch, sv, inputs, w, precision, tuned=None):
@@ -124,18 +135,12 @@ def tune(torch, sv, inputs, w, precision, tune_grid):
             first = layout_of(sv, prof[key + "_layout"])
             rest = [c for c in base if sv.layout_name(c) != sv.layout_name(first)]
             cands[key] = [first] + rest
-    res = st.autotune(candidates=cands, reps=3, cells_per_support=cps, h_ref=h_ref)
+    # between one bench run and the next the trial medians move by a few per
+    # cent: the first candidate within 3 % of the fastest is taken (the force
+    # loop is tuned after a density pass with the density layout so taken)
+    res = st.autotune(candidates=cands, reps=5, cells_per_support=cps, h_ref=h_ref, within=0.03)
     grid = tuple(st.p.grid)
     ld, lf = st.ld, st.lf
-    if cands:
-        # between one bench run and the next the trial medians move by a few
-        # per cent: the profiled layouts stay when within 3 % of the fastest
-        pick = {}
-        for key in ("density", "force"):
-            table = res[key][1]
-            lo = min(ms for _, ms in table)
-            pick[key] = next(c for c, ms in table if ms <= 1.03 * lo)
-        ld, lf = pick["density"], pick["force"]
     st.close()
     if tune_grid:
         log(f"[bench]   grid candidates (ms for cells_build + density + force): "
@@ -368,11 +373,13 @@ def main():
     achieved = flops / (ms_k / 1e3) / 1e12
     choice = choice_of(sv, t64)
     tr = measured_traffic(choice)
-    traffic = tr[kern] if tr else None
+    traffic, traffic_layout = tr.get(kern, (None, None))
     roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop, {choice[kern + '_layout']})",
                 "achieved": achieved,
                 "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VALU / 1e12),
                 "traffic": traffic,
+                # the counters' run used the same kernel; its layout, when another
+                "traffic_layout": traffic_layout,
                 "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12},
                 "force": {"ms": r64["ms_force"], "tflops": force_flops / (r64["ms_force"] / 1e3) / 1e12}}
 

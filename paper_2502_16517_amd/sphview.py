@@ -589,7 +589,8 @@ class Stepper:
         self._make_cells()
         self.set_layouts(self.ld, self.lf)
 
-    def autotune(self, candidates=None, reps: int = 3, cells_per_support=None, h_ref: float | None = None):
+    def autotune(self, candidates=None, reps: int = 3, cells_per_support=None, h_ref: float | None = None,
+                 within: float | None = None):
         """Picks the density and the force layouts on the current records (run
         after at least one step, so the force inputs are valid) and re-plans
         both views with them.  With cells_per_support (e.g. (1, 2)) it first
@@ -597,6 +598,9 @@ class Stepper:
         defaulting to the records' largest h, and rebuilds the cells on it.
         candidates: None (the built-in set), a list for both loops, or a dict
         with a list per loop ("density", "force"); earlier candidates win ties.
+        within: None keeps the library's choice (the first candidate within
+        1.5 % of the fastest); a fraction takes the first candidate within that
+        fraction of the fastest instead.
         The density layout is chosen first; the force layouts are then timed
         after one density pass with it (the records hold that pass's results
         afterwards).  Returns {"density": (best, table), "force": ...,
@@ -631,6 +635,10 @@ class Stepper:
             out[key] = autotune(loop, self.aos, d, self.cells, self.p, self.precision, ws, cands, reps,
                                 self.stream)
             del ws
+            if within is not None:
+                table = out[key][1]
+                lo = min(ms for _, ms in table)
+                out[key] = (next(c for c, ms in table if ms <= (1.0 + within) * lo), table)
             if loop == LOOP_DENSITY:
                 # the force loop reuses the density loop's cached candidate masks
                 # when both use the same lanes per particle; the density trials
