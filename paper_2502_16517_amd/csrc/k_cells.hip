@@ -430,8 +430,51 @@ __global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start,
         }
     }
     __syncthreads();
-    if (lane != 0) return;
     const bool px_ok = !g.periodic[0] || 2 * kGroupReach + 1 <= nx;
+    if (staged && nx <= kWave) {
+        // rows of at most 64 cells: lane x holds column x, and the whole wave
+        // walks the row with lane reads (the walk is scalar, no LDS round trips)
+        const int cnt = lane < nx ? scnt[lane] : 0;
+        const int rch = lane < nx ? srch[lane] : 0;
+        const int okl = lane < nx ? sok[lane] : 0;
+        int my_gx = 0, my_nit = 0;
+        int x = 0;
+        while (x < nx) {
+            const int c0 = __builtin_amdgcn_readlane(cnt, x);
+            const int r0 = __builtin_amdgcn_readlane(rch, x);
+            const int ok0 = __builtin_amdgcn_readlane(okl, x);
+            if (!(px_ok && ok0 && (c0 == 0 || r0 <= kGroupReach))) {
+                if (lane == x) {
+                    my_gx = 1;
+                    my_nit = (c0 + kWave - 1) / kWave;
+                }
+                ++x;
+                continue;
+            }
+            int R = c0 > 0 ? r0 : 0, tot = c0, gx = 1;
+            while (x + gx < nx && gx < kGroupLen && __builtin_amdgcn_readlane(okl, x + gx)) {
+                const int c2 = __builtin_amdgcn_readlane(cnt, x + gx);
+                if (tot + c2 > kGroupMax) break;
+                const int r2 = c2 > 0 ? __builtin_amdgcn_readlane(rch, x + gx) : 0;
+                if (r2 > kGroupReach || (c2 > 0 && R > 0 && r2 != R)) break;
+                if (g.periodic[0] && 2 * kGroupReach + gx + 1 > nx) break;
+                tot += c2;
+                R = R > r2 ? R : r2;
+                ++gx;
+            }
+            if (lane == x) {
+                my_gx = gx;
+                my_nit = tot > 0 ? 1 : 0;
+            }
+            x += gx;
+        }
+        if (lane < nx) {
+            gxo[base + lane] = my_gx;
+            nit[base + lane] = my_nit;
+        }
+        return;
+    }
+    if (lane != 0) return;
     int x = 0;
     while (x < nx) {
         const int c0 = staged ? scnt[x] : cell_start[base + x + 1] - cell_start[base + x];
