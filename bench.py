@@ -3,7 +3,7 @@
 One step = cells_build, the density view (gather, density with the
 smoothing-length iteration, scatter), the force view (gather, force, time-step
 and conservation reduction, scatter) and kick_drift, all through the C-ABI on
-one stream.  The workload is the two-state tube: a 64^3 lattice (density 1,
+one stream.  The workload (--workload, default tube64) is the two-state tube: a 64^3 lattice (density 1,
 pressure 1) beside a 32^3 lattice (density 1/8, pressure 0.1) in the periodic
 box [0,2]x[0,1]^2, 294,912 particles in 256-byte records, FP64.
 
@@ -99,11 +99,26 @@ def measured_traffic(choice):
     return {}
 
 
+# the synthetic workloads: generator, parameters other than the defaults, and
+# what they are
+WORKLOADS = {
+    "tube64": ("config2", {}, "two-state tube 64^3 + 32^3 = 294,912 particles, periodic [0,2]x[0,1]^2"),
+    "kh128": ("config3", {}, "Kelvin-Helmholtz shear layer 128^3 = 2,097,152 particles, periodic unit box"),
+    "plummer1M": ("config4", {"headroom": 1.6},
+                  "Plummer sphere a = 0.1 truncated at r = 1, 1,048,576 particles, open box [-1,1]^3, "
+                  "cells of 0.02 (1 to ~2000 particles)"),
+    "kh256": ("config5", {}, "Kelvin-Helmholtz shear layer 256^3 = 16,777,216 particles, periodic unit box"),
+}
+PKW = {}
+
+
 def make_stepper(torch, sv, inputs, w, precision, tuned=None):
     """A Stepper on the workload; tuned = (grid, density layout, force layout)."""
     grid, ld, lf = tuned if tuned else (tuple(w.grid), sv.layout(), sv.layout())
     p = sv.params_init(w.lo, w.length, grid, w.periodic)
     p.eta = w.eta
+    for k, v in PKW.items():
+        setattr(p, k, v)
     if precision == sv.PREC_FP32:
         p.h_tol = 1e-6
     st = sv.Stepper(w.rec, p, precision, layout_density=ld, layout_force=lf,
@@ -286,6 +301,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--workload", default="tube64", choices=list(WORKLOADS),
+                    help="tube64 is the headline; the others are the parity workloads, for context")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the tuner: SoA views for both loops")
     ap.add_argument("--layouts", default=None,
@@ -321,8 +338,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del src, dst
-    log("[bench] generating the two-state tube (294,912 particles)")
-    w = inputs.config2()
+    gen, pkw, desc = WORKLOADS[args.workload]
+    PKW.update(pkw)
+    log(f"[bench] generating the workload: {desc}")
+    w = getattr(inputs, gen)()
     if args.layouts:
         names = args.layouts.split(",")
         t64 = (tuple(w.grid), layout_of(sv, names[0]), layout_of(sv, names[1]))
@@ -399,7 +418,7 @@ def main():
             conv[name]["hbm_frac"] = conv[name]["GB/s"] * 1e9 / HBM_PEAK
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "tube64":
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(inputs, w)
 
@@ -416,8 +435,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "two-state tube 64^3 + 32^3 = 294,912 particles, periodic [0,2]x[0,1]^2, "
-                               "256-byte 32-slot records, FP64",
+        "config": {"workload": desc + ", 256-byte 32-slot records, FP64",
                    "n": w.n, "grid": list(t64[0]), "tuned": not (args.no_tune or args.layouts),
                    "layout": {"density": choice["density_layout"], "force": choice["force_layout"]},
                    "pairs_per_step": {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},

@@ -242,7 +242,9 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
 {
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) { char* p = base ? base + off : nullptr; off = align_up(off + bytes, kAlign); return p; };
-    int64_t max_items = nc + (n + kWave - 1) / kWave + 1;
+    // a non-empty cell of c particles gives ceil(c / 64) <= 1 + c / 64 items and a
+    // run of sparse cells one item, so items <= min(cells, particles) + n / 64
+    int64_t max_items = std::min<int64_t>(nc, n) + (n + kWave - 1) / kWave + 1;
     int64_t scan_blocks = (std::max(nc, max_items) + 1023) / 1024 + 1;
     c->key = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
     c->perm = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
