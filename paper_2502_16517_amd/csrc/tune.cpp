@@ -287,15 +287,19 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
         status = sphv_view_create(&v, d, n, &cand[k], precision, aos, (const int32_t*)info.perm, vws, vbytes);
         if (status) break;
         for (int r = 0; r < reps && status == SPHV_OK; ++r) {
+            bool moved = false;   // the records were moved into cell order by this trial
             status = sphv_state_init(state, stream);
             if (!status && hipEventRecord(ev.e0, s) != hipSuccess) status = SPHV_E_HIP;
-            if (!status && srt) status = sphv_records_sort(mc, aos, d->stride, ss.recs, ss.rec_bytes, stream);
+            if (!status && srt) {
+                status = sphv_records_sort(mc, aos, d->stride, ss.recs, ss.rec_bytes, stream);
+                moved = status == SPHV_OK;
+            }
             if (!status) status = sphv_aos_to_soa(v, cells, stream);
             if (!status) status = loop == SPHV_LOOP_DENSITY ? sphv_sph_density(v, cells, p, state, stream)
                                                             : sphv_sph_force(v, cells, p, state, stream);
             if (!status) status = sphv_soa_to_aos(v, stream);
             if (!status && hipEventRecord(ev.e1, s) != hipSuccess) status = SPHV_E_HIP;
-            if (srt && n > 0 && unsort(ss, *cells_dev(mc), aos, d->stride, s) != hipSuccess && !status)
+            if (moved && n > 0 && unsort(ss, *cells_dev(mc), aos, d->stride, s) != hipSuccess && !status)
                 status = SPHV_E_HIP;
             cells_set_sorted(mc, sorted_in);
             if (!status && n > 0 && restore(b, s) != hipSuccess) status = SPHV_E_HIP;
