@@ -183,9 +183,13 @@ def choice_of(sv, tuned):
             "force_layout": sv.layout_name(lf)}
 
 
+EVENTS = ("built", "d_gathered", "d_loop", "d_scattered", "f_gathered", "f_loop", "reduced", "f_scattered",
+          "kicked")
+
+
 def run_timed(torch, sv, st, steps, warmup, graph=False):
-    """Warm up, then time exactly `steps` steps; per-kernel HIP events around
-    the density and force pair loops on the same stream."""
+    """Warm up, then time exactly `steps` steps; HIP events on the stream
+    between the pieces of each step."""
     s = torch.cuda.current_stream()
     for _ in range(warmup):
         st.step()
@@ -197,7 +201,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         g = sv.graph_end(s)
         torch.cuda.synchronize()
     before = st.read_state()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(9)] for _ in range(steps)]
+    ev = [{name: torch.cuda.Event(enable_timing=True) for name in EVENTS} for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -206,25 +210,26 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         if graph:
             sv.graph_launch(g, s)
             continue
+        e = ev[k]
         sv.begin_step(st.state, s)
         sv.cells_build(st.cells, st.aos, st.d_cells, st.state, s)
-        ev[k][4].record(s)
+        e["built"].record(s)
         sv.aos_to_soa(st.v_dens, st.cells, s)
-        ev[k][0].record(s)
+        e["d_gathered"].record(s)
         sv.sph_density(st.v_dens, st.cells, st.p, st.state, s)
-        ev[k][1].record(s)
+        e["d_loop"].record(s)
         sv.soa_to_aos(st.v_dens, s)
-        ev[k][6].record(s)
+        e["d_scattered"].record(s)
         sv.aos_to_soa(st.v_force, st.cells, s)
-        ev[k][2].record(s)
+        e["f_gathered"].record(s)
         sv.sph_force(st.v_force, st.cells, st.p, st.state, s)
-        ev[k][3].record(s)
+        e["f_loop"].record(s)
         sv.step_reduce(st.v_force, st.p, st.state, s)
-        ev[k][7].record(s)
+        e["reduced"].record(s)
         sv.soa_to_aos(st.v_force, s)
-        ev[k][5].record(s)
+        e["f_scattered"].record(s)
         sv.kick_drift(st.aos, st.d_kick, st.n, st.p, st.state, s)
-        ev[k][8].record(s)
+        e["kicked"].record(s)
     e_end.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -233,16 +238,18 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
     res = dict(ms_total=ms, wall_s=wall, pairs=after.pairs_total - before.pairs_total,
                flags=after.flags, state=after)
     if not graph:
-        res["ms_density"] = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
-        res["ms_force"] = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+        span = lambda a, b: sum(x[a].elapsed_time(x[b]) for x in ev) / steps
+        res["ms_density"] = span("d_gathered", "d_loop")
+        # the force loop with its windows from the converged h
+        res["ms_force"] = span("f_gathered", "f_loop")
         # the span of the two views: first density gather to last force scatter
-        res["ms_span"] = sum(e[4].elapsed_time(e[5]) for e in ev) / steps
-        # the conversions and the linear kernels, each between its own events
-        for name, a, b in (("density_gather", 4, 0), ("density_scatter", 1, 6), ("force_gather", 6, 2),
-                           ("reduce", 3, 7), ("force_scatter", 7, 5), ("kick_drift", 5, 8)):
-            res["ms_" + name] = sum(e[a].elapsed_time(e[b]) for e in ev) / steps
-        log("[bench]   per-step density ms " + " ".join(f"{e[0].elapsed_time(e[1]):.3f}" for e in ev))
-        log("[bench]   per-step force ms   " + " ".join(f"{e[2].elapsed_time(e[3]):.3f}" for e in ev))
+        res["ms_span"] = span("built", "f_scattered")
+        for name, a, b in (("density_gather", "built", "d_gathered"), ("density_scatter", "d_loop", "d_scattered"),
+                           ("force_gather", "d_scattered", "f_gathered"), ("force_scatter", "reduced", "f_scattered"),
+                           ("kick_drift", "f_scattered", "kicked"), ("reduce", "f_loop", "reduced")):
+            res["ms_" + name] = span(a, b)
+        log("[bench]   per-step density ms " + " ".join(f"{x['d_gathered'].elapsed_time(x['d_loop']):.3f}" for x in ev))
+        log("[bench]   per-step force ms   " + " ".join(f"{x['f_gathered'].elapsed_time(x['f_loop']):.3f}" for x in ev))
     if g is not None:
         sv.graph_destroy(g)
     return res
@@ -447,6 +454,7 @@ def main():
         "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
         "conversions": conv,
+        "reduce_ms": r64["ms_reduce"],
         "hbm_frac_step": None,
     }
     # whole-step HBM fraction: algorithmic view bytes (gathers, scatters, loop
