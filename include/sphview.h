@@ -347,7 +347,7 @@ int32_t sphv_kick_drift(void* aos_dev, const sphv_descriptor* d, int64_t n,
  * the gather of A_in, the loop and the scatter of A_out of a view with that
  * layout, over the records aos_dev (described by d, indexed by the cells'
  * perm), starting from the records as they are.  Each candidate runs reps
- * trials; its figure is their median.  Medians within 1.5 % of the smallest
+ * trials, in reps rounds over all candidates; its figure is their median.  Medians within 1.5 % of the smallest
  * count as equal (timing noise): *best is the first such candidate in the
  * given order, so repeated tuning settles on one choice.  The medians, in
  * candidate order, go to ms (NULL: not reported).

@@ -279,14 +279,15 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
     Events ev;
     if (!ev.ok) return SPHV_E_HIP;
     int32_t status = SPHV_OK;
-    std::vector<float> meds;
-    std::vector<float> trial((size_t)reps);
-    for (int k = 0; k < n_cand && status == SPHV_OK; ++k) {
-        const bool srt = cand[k].kind == SPHV_LAYOUT_SORTED;
-        sphv_view* v = nullptr;
-        status = sphv_view_create(&v, d, n, &cand[k], precision, aos, (const int32_t*)info.perm, vws, vbytes);
-        if (status) break;
-        for (int r = 0; r < reps && status == SPHV_OK; ++r) {
+    // rounds over all candidates, reps times, so that a slow drift of the
+    // clocks during the call touches every candidate alike
+    std::vector<float> times((size_t)n_cand * (size_t)reps);
+    for (int r = 0; r < reps && status == SPHV_OK; ++r) {
+        for (int k = 0; k < n_cand && status == SPHV_OK; ++k) {
+            const bool srt = cand[k].kind == SPHV_LAYOUT_SORTED;
+            sphv_view* v = nullptr;
+            status = sphv_view_create(&v, d, n, &cand[k], precision, aos, (const int32_t*)info.perm, vws, vbytes);
+            if (status) break;
             bool moved = false;   // the records were moved into cell order by this trial
             status = sphv_state_init(state, stream);
             if (!status && hipEventRecord(ev.e0, s) != hipSuccess) status = SPHV_E_HIP;
@@ -304,13 +305,21 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
             cells_set_sorted(mc, sorted_in);
             if (!status && n > 0 && restore(b, s) != hipSuccess) status = SPHV_E_HIP;
             if (!status && hipEventSynchronize(ev.e1) != hipSuccess) status = SPHV_E_HIP;
-            if (!status && hipEventElapsedTime(&trial[(size_t)r], ev.e0, ev.e1) != hipSuccess) status = SPHV_E_HIP;
+            float ms = 0.f;
+            if (!status && hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) status = SPHV_E_HIP;
+            times[(size_t)k * reps + r] = ms;
+            sphv_view_destroy(v);   // also closes it when a call failed half way
         }
-        sphv_view_destroy(v);   // also closes it when a call failed half way
-        if (status) break;
-        const float med = median(trial);
-        if (ms_out) ms_out[k] = med;
-        meds.push_back(med);
+    }
+    std::vector<float> meds;
+    if (status == SPHV_OK) {
+        std::vector<float> trial((size_t)reps);
+        for (int k = 0; k < n_cand; ++k) {
+            for (int r = 0; r < reps; ++r) trial[(size_t)r] = times[(size_t)k * reps + r];
+            const float med = median(trial);
+            if (ms_out) ms_out[k] = med;
+            meds.push_back(med);
+        }
     }
     // the records as they came in, whatever happened above
     if (n > 0 && restore(b, s) != hipSuccess && status == SPHV_OK) status = SPHV_E_HIP;
