@@ -11,7 +11,8 @@
 //   segsort     perm[cell] = ascending record indices of the cell: the stable
 //               order (ties by index), key_sorted, density reach
 //   row groups  per row of cells: runs of sparse cells sharing one work item
-//   scan, items item_start; the items (cell, first, count <= 64, cells); n_items
+//   scan, items offsets of each cell's items, then the items (cell, first,
+//               count <= 64, cells) and n_items in the same second pass
 // and of the force window, at the start of sph_force, from the converged h:
 //   own reach per cell, separable box maximum over +-R_global, exact window.
 #include "k_common.h"
@@ -368,7 +369,7 @@ constexpr int kRowMax = 1024;   // rows up to this length are staged in LDS and 
 // whether every cell within +-kGroupReach of it (in x, y and z) is sparse;
 // lane 0 then walks the row.  For every cell c it leaves gx[c], the cells
 // covered by the items that start at c (0 inside a run), and nit[c], the number
-// of those items; k_items writes them at the exclusive scan of nit.
+// of those items; k_scan_items writes them at the exclusive scan of nit.
 __global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start, const int32_t* counts,
                                                       const int32_t* reach_d, Geom g, int32_t* nit, int32_t* gxo)
 {
@@ -506,32 +507,50 @@ __global__ __launch_bounds__(kWave) void k_row_groups(const int32_t* cell_start,
     }
 }
 
-__global__ void k_items(const int32_t* cell_start, const int32_t* item_start, const int32_t* gxo, int64_t nc,
-                        int64_t max_items, int4* items, int32_t* meta, DevState* st)
+// The second pass of the item scan and the item writes in one launch: each thread
+// scans its kScanItems cells' item counts (nit) as k_scan_apply does and
+// writes those cells' items at the offsets it just found.
+__global__ __launch_bounds__(kScanThreads) void k_scan_items(const int32_t* nit, int64_t nc, const int32_t* part,
+                                                             const int32_t* cell_start, const int32_t* gxo,
+                                                             int64_t max_items, int4* items, int32_t* meta,
+                                                             DevState* st)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c == 0) {
-        int total = item_start[nc];
-        if (total > max_items) {
+    __shared__ int lds[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < nc ? nit[base + k] : 0;
+        sum += v[k];
+    }
+    int total;
+    int o = block_scan_excl(sum, lds, total) + part[blockIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int all = part[gridDim.x];
+        if (all > max_items) {
             set_flag(st, SPHV_F_QUEUE_OVERFLOW);
-            total = (int)max_items;
+            all = (int)max_items;
         }
-        meta[META_NITEMS] = total;
+        meta[META_NITEMS] = all;
     }
-    if (c >= nc) return;
-    int o = item_start[c];
-    const int ni = item_start[c + 1] - o;
-    if (ni == 0) return;
-    const int gx = gxo[c];
-    const int b = cell_start[c];
-    if (gx > 1) {
-        if (o < max_items) items[o] = make_int4((int)c, b, cell_start[c + gx] - b, gx);
-        return;
-    }
-    const int e = cell_start[c + 1];
-    for (int f = b; f < e; f += kWave) {
-        if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 1);
-        ++o;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t c = base + k;
+        if (c >= nc || v[k] == 0) {
+            o += v[k];
+            continue;
+        }
+        const int gx = gxo[c];
+        const int b = cell_start[c];
+        if (gx > 1) {
+            if (o < max_items) items[o] = make_int4((int)c, b, cell_start[c + gx] - b, gx);
+            ++o;
+            continue;
+        }
+        const int e = cell_start[c + 1];
+        for (int f = b; f < e; f += kWave) {
+            if (o < max_items) items[o] = make_int4((int)c, f, min(kWave, e - f), 1);
+            ++o;
+        }
     }
 }
 
@@ -721,10 +740,15 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];
     hipLaunchKernelGGL(k_row_groups, dim3((unsigned)nrows), dim3(kWave), 0, s, c.cell_start, c.counts, c.reach_d, g,
                        c.tmp_a, c.tmp_b);
-    if ((e = scan_excl(c.tmp_a, c.nc, c.scan_part, c.item_start, nullptr, c.meta + META_SCAN + 1, s)) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_items, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.cell_start, c.item_start, c.tmp_b, c.nc,
-                       c.max_items, c.items, c.meta, st);
+    {
+        // item counts: block totals (the last block scans them), then offsets and items in one pass
+        int64_t nb = (c.nc + kScanTile - 1) / kScanTile;
+        if (nb == 0) nb = 1;
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, c.tmp_a, c.nc, c.scan_part,
+                           c.meta + META_SCAN + 1);
+        hipLaunchKernelGGL(k_scan_items, dim3((unsigned)nb), dim3(kScanThreads), 0, s, c.tmp_a, c.nc, c.scan_part,
+                           c.cell_start, c.tmp_b, c.max_items, c.items, c.meta, st);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipGetLastError();
 }
