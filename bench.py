@@ -262,6 +262,26 @@ def pair_evals_per_step(torch, sv, st):
     return s.pair_evals_density, s.pairs_force, s.pairs_density
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """The HBM rate a plain device-to-device copy reaches (bytes read + bytes
+    written per second, best of reps), beside the 8 TB/s of the specification."""
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        dst.copy_(src)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    rate = 2 * (mib << 20) / (best / 1e3)
+    return {"GB/s": rate / 1e9, "frac_of_peak": rate / HBM_PEAK, "bytes": 2 * (mib << 20), "ms": best}
+
+
 def cpu_baseline(inputs, w, reps=3):
     """The oracle (plain scalar C, OpenMP over its target particles, all host
     threads) on one step of the same workload: density with the h iteration
@@ -345,6 +365,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del src, dst
+    hbm_copy = None
+    if not args.calib_copy_mib:
+        hbm_copy = copy_bandwidth(torch)
+        log(f"[bench] device copy: {hbm_copy['GB/s']:.0f} GB/s (read + write)")
     gen, pkw, desc = WORKLOADS[args.workload]
     PKW.update(pkw)
     log(f"[bench] generating the workload: {desc}")
@@ -456,6 +480,7 @@ def main():
         "conversions": conv,
         "reduce_ms": r64["ms_reduce"],
         "hbm_frac_step": None,
+        "hbm_copy": hbm_copy,
     }
     # whole-step HBM fraction: algorithmic view bytes (gathers, scatters, loop
     # inputs and outputs) over the step time
