@@ -207,3 +207,31 @@ def test_ragged_sizes_step_matches_oracle(orc, drop):
     ref = before.copy()
     orc.kick_drift(ref, S, state.dt, 0.0, True, w.lo, w.length, w.periodic)
     assert np.array_equal(bits(ref), bits(after))
+
+
+def test_degenerate_sizes(orc):
+    """No particles: every call of a step succeeds and leaves nothing behind.
+    One particle: no pairs, so zero acceleration and heating and v_sig = 2 c;
+    its own kernel term alone cannot reach the density target, so h grows
+    until the cell cap stops it, which the status flags report."""
+    w0 = inputs.config1()
+    import dataclasses
+    for n in (0, 1):
+        w = dataclasses.replace(w0, rec=np.ascontiguousarray(w0.rec[:n]))
+        print(f"[degenerate] n={n}", flush=True)
+        st = sv.Stepper(w.rec, sv.params_for(w))
+        st.step()
+        out = st.records()
+        state = st.read_state()
+        st.close()
+        assert out.shape == (n, inputs.NSLOT)
+        if n == 0:
+            assert state.flags == 0 and state.pairs_density == 0 and state.pairs_force == 0
+            continue
+        assert state.pairs_density == 0 and state.pairs_force == 0
+        assert state.flags & (sv.F_H_CAP_HIT | sv.F_H_NOT_CONVERGED)
+        assert np.all(np.isfinite(out[:, [S[k] for k in ("h", "rho", "omega", "x", "y", "z")]]))
+        assert out[0, S["ax"]] == 0.0 and out[0, S["ay"]] == 0.0 and out[0, S["az"]] == 0.0
+        assert out[0, S["u_dt"]] == 0.0
+        c = np.sqrt(inputs.GAMMA * (inputs.GAMMA - 1.0) * w.rec[0, S["u"]])
+        assert abs(out[0, S["v_sig"]] / (2.0 * c) - 1.0) < 1e-15
