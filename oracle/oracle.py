@@ -50,22 +50,23 @@ def lib():
             from . import build as _b  # noqa: WPS433
             _b.build()
         L = C.CDLL(path)
-        for name in ("orc_w", "orc_dw"):
+        for name in ("orc_w", "orc_dw", "orc_w5", "orc_dw5"):
             getattr(L, name).restype = C.c_double
             getattr(L, name).argtypes = [C.c_double]
         for name in ("orc_W", "orc_dWdr", "orc_dWdh"):
             getattr(L, name).restype = C.c_double
-            getattr(L, name).argtypes = [C.c_double, C.c_double]
+            getattr(L, name).argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_density_at.restype = C.c_int
         L.orc_density_at.argtypes = [C.c_int64, D, D, D, D, C.POINTER(Box), C.c_int32, C.c_double,
-                                     C.c_int64, I64, D, D, D, D, I64, C.c_int32]
+                                     C.c_int64, I64, D, D, D, D, I64, C.c_int32, C.c_int32]
         L.orc_density.restype = C.c_int
         L.orc_density.argtypes = [C.c_int64, D, D, D, D, D, C.POINTER(Box), C.c_double, C.c_double,
                                   C.c_int32, C.c_int32, C.c_double, C.c_int64, I64,
-                                  D, D, D, D, D, D, I64, I32, I32, C.c_int32]
+                                  D, D, D, D, D, D, I64, I32, I32, C.c_int32, C.c_int32]
         L.orc_force.restype = C.c_int
         L.orc_force.argtypes = [C.c_int64] + [D] * 12 + [C.POINTER(Box), C.c_double, C.c_int32,
-                                                         C.c_double, C.c_int64, I64] + [D] * 7 + [I64, C.c_int32]
+                                                         C.c_double, C.c_int64, I64] + [D] * 7 + \
+                               [I64, C.c_int32, C.c_int32]
         L.orc_max_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -81,24 +82,37 @@ def _c64(a):
 
 # ------------------------------------------------------------------ kernel
 
-def w(q: float) -> float:
-    return lib().orc_w(float(q))
+# kernel ids: 0 the cubic M4 spline, 1 the quartic M5 spline (both support 2h)
+CUBIC, QUARTIC = 0, 1
 
 
-def dw(q: float) -> float:
-    return lib().orc_dw(float(q))
+def _kernel(kernel) -> int:
+    k = int(kernel)
+    if k not in (CUBIC, QUARTIC):
+        raise ValueError(f"unknown kernel {kernel}")
+    return k
 
 
-def W(r: float, h: float) -> float:
-    return lib().orc_W(float(r), float(h))
+def w(q: float, kernel: int = CUBIC) -> float:
+    L = lib()
+    return (L.orc_w5 if _kernel(kernel) == QUARTIC else L.orc_w)(float(q))
 
 
-def dWdr(r: float, h: float) -> float:
-    return lib().orc_dWdr(float(r), float(h))
+def dw(q: float, kernel: int = CUBIC) -> float:
+    L = lib()
+    return (L.orc_dw5 if _kernel(kernel) == QUARTIC else L.orc_dw)(float(q))
 
 
-def dWdh(r: float, h: float) -> float:
-    return lib().orc_dWdh(float(r), float(h))
+def W(r: float, h: float, kernel: int = CUBIC) -> float:
+    return lib().orc_W(_kernel(kernel), float(r), float(h))
+
+
+def dWdr(r: float, h: float, kernel: int = CUBIC) -> float:
+    return lib().orc_dWdr(_kernel(kernel), float(r), float(h))
+
+
+def dWdh(r: float, h: float, kernel: int = CUBIC) -> float:
+    return lib().orc_dWdh(_kernel(kernel), float(r), float(h))
 
 
 # --------------------------------------------------- view conversions (exact)
@@ -163,7 +177,7 @@ def sort_cells(keys, ncell):
 # ---------------------------------------------------------- pair sums (C)
 
 def density(x, y, z, m, h0, box: Box, eta, tol=1e-13, max_iter=16, brute=False,
-            cell_hint=None, targets=None, nthreads=0):
+            cell_hint=None, targets=None, nthreads=0, kernel=CUBIC):
     """Density with the smoothing-length iteration at the given targets."""
     x, y, z, m, h0 = map(_c64, (x, y, z, m, h0))
     n = x.shape[0]
@@ -179,14 +193,15 @@ def density(x, y, z, m, h0, box: Box, eta, tol=1e-13, max_iter=16, brute=False,
                            int(brute), cell_hint, nt, t.ctypes.data_as(I64),
                            _d(out["h"]), _d(out["rho"]), _d(out["omega"]), _d(out["wcount"]),
                            _d(out["drho"]), _d(out["sdrho"]), cnt.ctypes.data_as(I64),
-                           its.ctypes.data_as(I32), conv.ctypes.data_as(I32), nthreads)
+                           its.ctypes.data_as(I32), conv.ctypes.data_as(I32), nthreads, _kernel(kernel))
     if rc != 0:
         raise MemoryError("oracle density failed")
     out.update(count=cnt, iters=its, converged=conv)
     return out
 
 
-def density_at(x, y, z, m, h_eval, box: Box, brute=False, cell_hint=None, targets=None, nthreads=0):
+def density_at(x, y, z, m, h_eval, box: Box, brute=False, cell_hint=None, targets=None, nthreads=0,
+               kernel=CUBIC):
     """Density sums at fixed h (no iteration) at the given targets."""
     x, y, z, m = map(_c64, (x, y, z, m))
     n = x.shape[0]
@@ -198,14 +213,14 @@ def density_at(x, y, z, m, h_eval, box: Box, brute=False, cell_hint=None, target
     cnt = np.zeros(t.shape[0], dtype=np.int64)
     rc = lib().orc_density_at(n, _d(x), _d(y), _d(z), _d(m), C.byref(box), int(brute), cell_hint,
                               t.shape[0], t.ctypes.data_as(I64), _d(he), _d(rho), _d(drho), _d(nsum),
-                              cnt.ctypes.data_as(I64), nthreads)
+                              cnt.ctypes.data_as(I64), nthreads, _kernel(kernel))
     if rc != 0:
         raise MemoryError("oracle density_at failed")
     return dict(rho=rho, drho=drho, nsum=nsum, count=cnt)
 
 
 def force(x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha, box: Box, gamma=5.0 / 3.0,
-          brute=False, cell_hint=None, targets=None, nthreads=0):
+          brute=False, cell_hint=None, targets=None, nthreads=0, kernel=CUBIC):
     """Force (pressure with grad-h terms + signal-velocity viscosity) at targets."""
     arrs = list(map(_c64, (x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha)))
     n = arrs[0].shape[0]
@@ -218,7 +233,7 @@ def force(x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha, box: Box, gamma=5.0 /
     rc = lib().orc_force(n, *[_d(a) for a in arrs], C.byref(box), gamma, int(brute), cell_hint,
                          nt, t.ctypes.data_as(I64), _d(out["ax"]), _d(out["ay"]), _d(out["az"]),
                          _d(out["udot"]), _d(out["vsig"]), _d(out["sa"]), _d(out["su"]),
-                         cnt.ctypes.data_as(I64), nthreads)
+                         cnt.ctypes.data_as(I64), nthreads, _kernel(kernel))
     if rc != 0:
         raise MemoryError("oracle force failed")
     out["count"] = cnt
@@ -291,19 +306,21 @@ def kick_drift(rec: np.ndarray, slot: dict, dt: float, dt_prev: float, first_ste
 
 def step_fp64(rec: np.ndarray, slot: dict, box: Box, eta: float, cfl: float, gamma: float,
               tol: float = 1e-13, max_iter: int = 16, dt_prev: float = 0.0,
-              first_step: bool = True, lo=None, length=None, periodic=None, nthreads=0):
+              first_step: bool = True, lo=None, length=None, periodic=None, nthreads=0,
+              kernel: int = CUBIC):
     """One FP64 step on the records in place: density, force, dt, kick/drift.
     Returns a dict with dt, the pair counts and the per-particle outputs."""
     col = {k: rec[:, slot[k]] for k in slot}
     d = density(col["x"], col["y"], col["z"], col["m"], col["h"], box, eta, tol, max_iter,
-                nthreads=nthreads)
+                nthreads=nthreads, kernel=kernel)
     rec[:, slot["h"]] = d["h"]
     rec[:, slot["rho"]] = d["rho"]
     rec[:, slot["omega"]] = d["omega"]
     rec[:, slot["wcount"]] = d["wcount"]
     col = {k: rec[:, slot[k]] for k in slot}
     f = force(col["x"], col["y"], col["z"], col["vx"], col["vy"], col["vz"], col["m"], col["h"],
-              col["rho"], col["omega"], col["u"], col["alpha"], box, gamma, nthreads=nthreads)
+              col["rho"], col["omega"], col["u"], col["alpha"], box, gamma, nthreads=nthreads,
+              kernel=kernel)
     rec[:, slot["ax"]] = f["ax"]
     rec[:, slot["ay"]] = f["ay"]
     rec[:, slot["az"]] = f["az"]

@@ -14,13 +14,15 @@
  *    kick / drift / kick) is the paper's SPH blueprint (Sec. 2.1).
  *  - Pairs are (local i, active j), j != i, filtered by a radius predicate;
  *    out-of-range pairs contribute the neutral element (Sec. 2.3, Sec. 5.6).
- *  - The paper names the formulas only by citation.  The kernel is the cubic
- *    M4 spline of Monaghan & Lattanzio with support 2h; density / grad-h terms
+ *  - The paper names the formulas only by citation.  Two kernels, both with
+ *    support 2h: the cubic M4 spline of Monaghan & Lattanzio (kernel 0) and the
+ *    quartic M5 spline the paper employs (Sec. 2.1, kernel 1); density / grad-h terms
  *    follow Springel & Hernquist 2002 and Price 2012; the artificial viscosity
  *    is the signal-velocity form of Monaghan 1997 as used by Springel 2005.
  *
  * Pins (tests/test_oracle_*.py): kernel normalisation by quadrature, finite-
- * difference derivatives, textbook spline values, lattice neighbour counts and
+ * difference derivatives, textbook spline values, the quartic against scipy's
+ * degree-4 B-spline (Cox-de Boor), lattice neighbour counts and
  * lattice sums, brute force == cell list, momentum / energy conservation,
  * adiabatic du/dt == (P/rho^2) drho/dt by finite differences, the pressure
  * force == -grad of the thermal energy by finite differences.
@@ -53,15 +55,54 @@ double orc_dw(double q)
     return 0.0;
 }
 
+/*
+ * Quartic M5 spline (Monaghan 1985), the kernel the paper employs (Sec. 2.1).
+ * In its own variable s, with support s < 2.5, its shape is
+ *   f(s) = (2.5-s)^4 - 5 (1.5-s)^4 + 10 (0.5-s)^4   for 0   <= s < 0.5,
+ *   f(s) = (2.5-s)^4 - 5 (1.5-s)^4                  for 0.5 <= s < 1.5,
+ *   f(s) = (2.5-s)^4                                for 1.5 <= s < 2.5,
+ * and f(r/h')/(20 pi h'^3) integrates to one in three dimensions.  Reading:
+ * it is scaled to the same support 2h as the cubic (h' = 0.8 h, s = 1.25 q),
+ * so cells, reach and the pair predicate do not depend on the kernel; then
+ * W = w(q)/(pi h^3) with w(q) = f(1.25 q) / 10.24, since 20 * 0.8^3 = 10.24.
+ */
+double orc_w5(double q)
+{
+    double s = 1.25 * q;
+    if (s >= 2.5) return 0.0;
+    double a = 2.5 - s;
+    double f = a * a * a * a;
+    if (s < 1.5) { double b = 1.5 - s; f -= 5.0 * b * b * b * b; }
+    if (s < 0.5) { double c = 0.5 - s; f += 10.0 * c * c * c * c; }
+    return f / 10.24;
+}
+
+/* dw/dq of the M5 spline: 1.25 f'(s) / 10.24. */
+double orc_dw5(double q)
+{
+    double s = 1.25 * q;
+    if (s >= 2.5) return 0.0;
+    double a = 2.5 - s;
+    double fp = -4.0 * a * a * a;
+    if (s < 1.5) { double b = 1.5 - s; fp += 20.0 * b * b * b; }
+    if (s < 0.5) { double c = 0.5 - s; fp -= 40.0 * c * c * c; }
+    return 1.25 * fp / 10.24;
+}
+
+/* kernel 0: cubic M4, kernel 1: quartic M5 */
+static double kw(int32_t kernel, double q) { return kernel == 1 ? orc_w5(q) : orc_w(q); }
+static double kdw(int32_t kernel, double q) { return kernel == 1 ? orc_dw5(q) : orc_dw(q); }
+static int kernel_ok(int32_t kernel) { return kernel == 0 || kernel == 1; }
+
 /* W(r,h) = w(r/h) / (pi h^3) */
-double orc_W(double r, double h) { return orc_w(r / h) / (ORC_PI * h * h * h); }
+double orc_W(int32_t kernel, double r, double h) { return kw(kernel, r / h) / (ORC_PI * h * h * h); }
 /* dW/dr */
-double orc_dWdr(double r, double h) { return orc_dw(r / h) / (ORC_PI * h * h * h * h); }
+double orc_dWdr(int32_t kernel, double r, double h) { return kdw(kernel, r / h) / (ORC_PI * h * h * h * h); }
 /* dW/dh = -(3 w + q w') / (pi h^4) */
-double orc_dWdh(double r, double h)
+double orc_dWdh(int32_t kernel, double r, double h)
 {
     double q = r / h;
-    return -(3.0 * orc_w(q) + q * orc_dw(q)) / (ORC_PI * h * h * h * h);
+    return -(3.0 * kw(kernel, q) + q * kdw(kernel, q)) / (ORC_PI * h * h * h * h);
 }
 
 /* -------------------------------------------------------------- geometry */
@@ -202,13 +243,13 @@ typedef struct {
     int64_t count;   /* pairs j != i inside the support */
 } dacc;
 
-static void dens_pair(dacc* a, double r2, double h, double mj, int self)
+static void dens_pair(dacc* a, int32_t kernel, double r2, double h, double mj, int self)
 {
     double H = 2.0 * h;
     if (!(r2 < H * H)) return;
     double r = sqrt(r2);
     double q = r / h;
-    double w = orc_w(q), dw = orc_dw(q);
+    double w = kw(kernel, q), dw = kdw(kernel, q);
     double norm = 1.0 / (ORC_PI * h * h * h);
     double Wv = w * norm;
     double dWh = -(3.0 * w + q * dw) * norm / h;
@@ -223,6 +264,7 @@ typedef struct {
     int64_t n;
     const double *x, *y, *z, *m;
     const orc_box* bx;
+    int32_t kernel;
 } pset;
 
 static void dens_sums(const pset* P, const ogrid* g, int64_t i, double h, dacc* a)
@@ -235,7 +277,7 @@ static void dens_sums(const pset* P, const ogrid* g, int64_t i, double h, dacc* 
             double dy = mi(yi, P->y[j], P->bx, 1);
             double dz = mi(zi, P->z[j], P->bx, 2);
             double r2 = dx * dx + dy * dy + dz * dz;
-            dens_pair(a, r2, h, P->m[j], j == i);
+            dens_pair(a, P->kernel, r2, h, P->m[j], j == i);
         }
         return;
     }
@@ -259,7 +301,7 @@ static void dens_sums(const pset* P, const ogrid* g, int64_t i, double h, dacc* 
                     double dy = mi(yi, P->y[j], P->bx, 1);
                     double dz = mi(zi, P->z[j], P->bx, 2);
                     double r2 = dx * dx + dy * dy + dz * dz;
-                    dens_pair(a, r2, h, P->m[j], j == i);
+                    dens_pair(a, P->kernel, r2, h, P->m[j], j == i);
                 }
             }
         }
@@ -273,9 +315,11 @@ static void dens_sums(const pset* P, const ogrid* g, int64_t i, double h, dacc* 
 int orc_density_at(int64_t n, const double* x, const double* y, const double* z, const double* m,
                    const orc_box* bx, int32_t brute, double cell_hint,
                    int64_t nt, const int64_t* targets, const double* h_eval,
-                   double* rho, double* drho, double* nsum, int64_t* count, int32_t nthreads)
+                   double* rho, double* drho, double* nsum, int64_t* count, int32_t nthreads,
+                   int32_t kernel)
 {
-    pset P = {n, x, y, z, m, bx};
+    if (!kernel_ok(kernel)) return -2;
+    pset P = {n, x, y, z, m, bx, kernel};
     ogrid G, *g = NULL;
     if (!brute) { if (grid_build(&G, n, x, y, z, NULL, bx, cell_hint)) return -1; g = &G; }
 #ifdef _OPENMP
@@ -311,9 +355,10 @@ int orc_density(int64_t n, const double* x, const double* y, const double* z, co
                 int32_t brute, double cell_hint, int64_t nt, const int64_t* targets,
                 double* out_h, double* out_rho, double* out_omega, double* out_wcount,
                 double* out_drho, double* out_sdrho, int64_t* out_count, int32_t* out_iters,
-                int32_t* out_conv, int32_t nthreads)
+                int32_t* out_conv, int32_t nthreads, int32_t kernel)
 {
-    pset P = {n, x, y, z, m, bx};
+    if (!kernel_ok(kernel)) return -2;
+    pset P = {n, x, y, z, m, bx, kernel};
     ogrid G, *g = NULL;
     if (!brute) { if (grid_build(&G, n, x, y, z, NULL, bx, cell_hint)) return -1; g = &G; }
     const double eta3 = eta * eta * eta;
@@ -367,6 +412,7 @@ typedef struct {
     const double *x, *y, *z, *vx, *vy, *vz, *m, *h, *rho, *omega, *u, *alpha;
     const orc_box* bx;
     double gamma;
+    int32_t kernel;
 } fset;
 
 typedef struct {
@@ -394,8 +440,8 @@ static void force_pair(const fset* F, int64_t i, int64_t j, facc* a)
     double Ai = Pi_ / (F->omega[i] * F->rho[i] * F->rho[i]);
     double Aj = Pj_ / (F->omega[j] * F->rho[j] * F->rho[j]);
     double r = sqrt(r2);
-    double gi = orc_dWdr(r, hi);                  /* 0 outside 2 h_i */
-    double gj = orc_dWdr(r, hj);
+    double gi = orc_dWdr(F->kernel, r, hi);       /* 0 outside 2 h_i */
+    double gj = orc_dWdr(F->kernel, r, hj);
     double gbar = 0.5 * (gi + gj);
     double ex = dx / r, ey = dy / r, ez = dz / r;
     double dvx = F->vx[i] - F->vx[j], dvy = F->vy[i] - F->vy[j], dvz = F->vz[i] - F->vz[j];
@@ -433,9 +479,10 @@ int orc_force(int64_t n, const double* x, const double* y, const double* z,
               double cell_hint, int64_t nt, const int64_t* targets,
               double* out_ax, double* out_ay, double* out_az, double* out_udot,
               double* out_vsig, double* out_sa, double* out_su, int64_t* out_count,
-              int32_t nthreads)
+              int32_t nthreads, int32_t kernel)
 {
-    fset F = {n, x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha, bx, gamma};
+    if (!kernel_ok(kernel)) return -2;
+    fset F = {n, x, y, z, vx, vy, vz, m, h, rho, omega, u, alpha, bx, gamma, kernel};
     ogrid G, *g = NULL;
     double hglob = 0.0;
     for (int64_t i = 0; i < n; ++i) if (h[i] > hglob) hglob = h[i];

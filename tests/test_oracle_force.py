@@ -13,7 +13,8 @@ from paper_2502_16517_amd import inputs
 G = 5.0 / 3.0
 
 
-def state(n_side=8, seed=3, jitter=0.15, periodic=True, vscale=0.3, alpha=0.8, converge=True, orc=None):
+def state(n_side=8, seed=3, jitter=0.15, periodic=True, vscale=0.3, alpha=0.8, converge=True, orc=None,
+          kernel=0):
     w = inputs.lattice_box(n_side, seed, jitter=jitter)
     S = inputs.SLOT
     r = w.rec
@@ -26,7 +27,8 @@ def state(n_side=8, seed=3, jitter=0.15, periodic=True, vscale=0.3, alpha=0.8, c
     c["alpha"] = np.full(n, alpha)
     per = (1, 1, 1) if periodic else (0, 0, 0)
     box = orc.box_of(w.lo, w.length, per)
-    d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, eta=1.2, tol=1e-14, max_iter=30)
+    d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, eta=1.2, tol=1e-14, max_iter=30,
+                    kernel=kernel)
     assert np.all(d["converged"] == 1)
     c["h"], c["rho"], c["omega"] = d["h"], d["rho"], d["omega"]
     return c, box
@@ -37,10 +39,11 @@ def run_force(orc, c, box, **kw):
                      c["omega"], c["u"], c["alpha"], box, G, **kw)
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("periodic", [True, False])
-def test_momentum_and_energy_conservation(orc, periodic):
-    c, box = state(periodic=periodic, orc=orc)
-    f = run_force(orc, c, box)
+def test_momentum_and_energy_conservation(orc, periodic, kernel):
+    c, box = state(periodic=periodic, orc=orc, kernel=kernel)
+    f = run_force(orc, c, box, kernel=kernel)
     m = c["m"]
     scale = np.sum(m * f["sa"])
     for k in ("ax", "ay", "az"):
@@ -92,18 +95,19 @@ def test_unjittered_lattice_is_in_equilibrium(orc):
     assert orc.time_step(d["h"], f["vsig"], 0.3) == 0.3 * (d["h"].min() / (2.0 * cs))
 
 
-def test_adiabatic_udot_matches_density_rate(orc):
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_adiabatic_udot_matches_density_rate(orc, kernel):
     """Without viscosity du_i/dt = (P_i / rho_i^2) d rho_i/dt along the flow,
     with h following rho h^3 = m eta^3 (the grad-h construction)."""
-    c, box = state(alpha=0.0, jitter=0.2, orc=orc)
-    f = run_force(orc, c, box)
+    c, box = state(alpha=0.0, jitter=0.2, orc=orc, kernel=kernel)
+    f = run_force(orc, c, box, kernel=kernel)
     dt = 1e-6
     dens = []
     for sgn in (+1, -1):
         x = c["x"] + sgn * dt * c["vx"]
         y = c["y"] + sgn * dt * c["vy"]
         z = c["z"] + sgn * dt * c["vz"]
-        d = orc.density(x, y, z, c["m"], c["h"], box, eta=1.2, tol=1e-15, max_iter=40)
+        d = orc.density(x, y, z, c["m"], c["h"], box, eta=1.2, tol=1e-15, max_iter=40, kernel=kernel)
         dens.append(d["rho"])
     drho = (dens[0] - dens[1]) / (2 * dt)
     P = (G - 1.0) * c["rho"] * c["u"]
@@ -111,11 +115,12 @@ def test_adiabatic_udot_matches_density_rate(orc):
     assert np.max(np.abs(f["udot"] - expect) / (f["su"] + 1e-30)) < 2e-6
 
 
-def test_pressure_force_is_minus_energy_gradient(orc):
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_pressure_force_is_minus_energy_gradient(orc, kernel):
     """The grad-h pressure force derives from the thermal energy U = sum m_j u_j
     at fixed entropy u_j / rho_j^(gamma-1): m_i a_i = -dU/dx_i."""
-    c, box = state(alpha=0.0, n_side=7, jitter=0.2, orc=orc)
-    f = run_force(orc, c, box)
+    c, box = state(alpha=0.0, n_side=7, jitter=0.2, orc=orc, kernel=kernel)
+    f = run_force(orc, c, box, kernel=kernel)
     K = c["u"] / c["rho"] ** (G - 1.0)
     eps = 2e-7
     for i in (0, 17, 101):
@@ -125,7 +130,7 @@ def test_pressure_force_is_minus_energy_gradient(orc):
                 p = {k: c[k].copy() for k in ("x", "y", "z")}
                 p[key][i] += sgn * eps
                 d = orc.density(p["x"], p["y"], p["z"], c["m"], c["h"], box, eta=1.2, tol=1e-15,
-                                max_iter=40)
+                                max_iter=40, kernel=kernel)
                 Us.append(math.fsum(c["m"] * K * d["rho"] ** (G - 1.0)))
             F = -(Us[0] - Us[1]) / (2 * eps)
             a = f[("ax", "ay", "az")[axis]][i]
