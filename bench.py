@@ -32,9 +32,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # algorithmic flops per true pair (FMA = 2, sqrt and division = 1 each), counted
-# on the pair formulas of the density and force loops
-FLOPS_DENSITY_PAIR = 26
-FLOPS_FORCE_PAIR = 67
+# on the pair formulas of the density and force loops, per smoothing kernel: the
+# quartic's w and w' take 11 more than the cubic's, its w' alone 7 more (twice
+# per force pair)
+FLOPS_DENSITY_PAIR = {"cubic": 26, "quartic": 37}
+FLOPS_FORCE_PAIR = {"cubic": 67, "quartic": 81}
 PEAK_FP64_VALU = 256 * 2.4e9 * 128          # 256 CUs x 2.4 GHz x 64 FMA lanes: 78.6 TFLOP/s
 PEAK_FP32_VALU = 157.3e12                   # published, needs packed FP32
 HBM_PEAK = 8.0e12
@@ -110,6 +112,8 @@ WORKLOADS = {
     "kh256": ("config5", {}, "Kelvin-Helmholtz shear layer 256^3 = 16,777,216 particles, periodic unit box"),
 }
 PKW = {}
+# smoothing kernels (the library's kernel ids)
+KERNELS = {"cubic": 0, "quartic": 1}
 
 
 def make_stepper(torch, sv, inputs, w, precision, tuned=None):
@@ -282,7 +286,7 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return {"GB/s": rate / 1e9, "frac_of_peak": rate / HBM_PEAK, "bytes": 2 * (mib << 20), "ms": best}
 
 
-def cpu_baseline(inputs, w, reps=3):
+def cpu_baseline(inputs, w, kernel=0, reps=3):
     """The oracle (plain scalar C, OpenMP over its target particles, all host
     threads) on one step of the same workload: density with the h iteration
     for every particle, then the force for every particle from the oracle's own
@@ -299,10 +303,10 @@ def cpu_baseline(inputs, w, reps=3):
     td = tf = 0.0
     for _ in range(reps):
         t0 = time.perf_counter()
-        d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads)
+        d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads, kernel=kernel)
         t1 = time.perf_counter()
         f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], d["h"], d["rho"], d["omega"],
-                      c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads)
+                      c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads, kernel=kernel)
         t2 = time.perf_counter()
         td += t1 - t0
         tf += t2 - t1
@@ -328,6 +332,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--kernel", default="cubic", choices=list(KERNELS),
+                    help="smoothing kernel of the measured step: the cubic M4 spline, or the quartic M5 the "
+                         "paper employs")
+    ap.add_argument("--no-other-kernel", action="store_true",
+                    help="skip the extra timing of the other smoothing kernel with the same layouts")
     ap.add_argument("--workload", default="tube64", choices=list(WORKLOADS),
                     help="tube64 is the headline; the others are the parity workloads, for context")
     ap.add_argument("--no-tune", action="store_true",
@@ -371,6 +380,7 @@ def main():
         log(f"[bench] device copy: {hbm_copy['GB/s']:.0f} GB/s (read + write)")
     gen, pkw, desc = WORKLOADS[args.workload]
     PKW.update(pkw)
+    PKW["kernel"] = KERNELS[args.kernel]
     log(f"[bench] generating the workload: {desc}")
     w = getattr(inputs, gen)()
     if args.layouts:
@@ -395,6 +405,19 @@ def main():
     g64 = run_timed(torch, sv, st, args.steps, args.warmup, graph=True)
     st.close()
 
+    other = None
+    if not args.no_other_kernel:
+        oname = next(k for k in KERNELS if k != args.kernel)
+        log(f"[bench] fp64 eager, {oname} kernel, same layouts")
+        PKW["kernel"] = KERNELS[oname]
+        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, t64)
+        ro = run_timed(torch, sv, st, args.steps, args.warmup)
+        st.close()
+        PKW["kernel"] = KERNELS[args.kernel]
+        other = {"kernel": oname, "value": ro["pairs"] / (ro["ms_total"] / 1e3),
+                 "ms_per_step": ro["ms_total"] / args.steps, "ms_density": ro["ms_density"],
+                 "ms_force": ro["ms_force"], "flags": ro["flags"]}
+
     f32 = None
     if not args.no_fp32:
         if args.no_tune:
@@ -414,15 +437,15 @@ def main():
     ms_step = r64["ms_total"] / args.steps
     value = r64["pairs"] / (r64["ms_total"] / 1e3)
     # dominant kernel: the larger of the two pair loops
-    dens_flops = evals_d * FLOPS_DENSITY_PAIR
-    force_flops = pairs_f * FLOPS_FORCE_PAIR
+    dens_flops = evals_d * FLOPS_DENSITY_PAIR[args.kernel]
+    force_flops = pairs_f * FLOPS_FORCE_PAIR[args.kernel]
     if r64["ms_force"] >= r64["ms_density"]:
         kern, flops, ms_k = "force", force_flops, r64["ms_force"]
     else:
         kern, flops, ms_k = "density", dens_flops, r64["ms_density"]
     achieved = flops / (ms_k / 1e3) / 1e12
     choice = choice_of(sv, t64)
-    tr = measured_traffic(choice)
+    tr = measured_traffic(choice) if args.kernel == "cubic" else {}
     traffic, traffic_layout = tr.get(kern, (None, None))
     roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop, {choice[kern + '_layout']})",
                 "achieved": achieved,
@@ -451,7 +474,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tube64":
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(inputs, w)
+        cpu = cpu_baseline(inputs, w, KERNELS[args.kernel])
 
     out = {
         "metric": "pair interactions/s (density+force incl. AoS<->SoA views)",
@@ -468,6 +491,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc + ", 256-byte 32-slot records, FP64",
                    "n": w.n, "grid": list(t64[0]), "tuned": not (args.no_tune or args.layouts),
+                   "kernel": args.kernel,
                    "layout": {"density": choice["density_layout"], "force": choice["force_layout"]},
                    "pairs_per_step": {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
         "roofline": roofline,
@@ -477,6 +501,7 @@ def main():
         # without cells_build and kick_drift
         "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
+        "other_kernel": other,
         "conversions": conv,
         "reduce_ms": r64["ms_reduce"],
         "hbm_frac_step": None,

@@ -133,10 +133,22 @@ typedef struct {
     double h_tol;      /* Newton stop |h+ - h| <= h_tol h                         */
     double headroom;   /* cell reach: R = ceil(2 h headroom / min cell), >= 1     */
     int32_t max_iter;  /* density passes, 1..64                                   */
-    int32_t reserved;
+    int32_t kernel;    /* smoothing kernel, SPHV_KERNEL_CUBIC or SPHV_KERNEL_QUARTIC */
 } sphv_params;
 
-/* Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16. */
+/* Smoothing kernels W(r, h) = w(q) / (pi h^3), q = r/h, both with support
+ * r < 2h, so cells, reach and the pair predicate do not depend on the choice:
+ *  - SPHV_KERNEL_CUBIC: the cubic M4 spline (Monaghan & Lattanzio),
+ *    w = (2-q)_+^3 / 4 - (1-q)_+^3;
+ *  - SPHV_KERNEL_QUARTIC: the quartic M5 spline the paper employs (Sec. 2.1,
+ *    after Monaghan 1985), its knots 0.5, 1.5, 2.5 of s = 1.25 q placed at
+ *    q = 0.4, 1.2, 2: w = (15625/65536) ((2-q)_+^4 - 5 (1.2-q)_+^4 + 10 (0.4-q)_+^4).
+ * Any other value is rejected with SPHV_E_INVALID_ARG by every call that
+ * takes parameters. */
+enum { SPHV_KERNEL_CUBIC = 0, SPHV_KERNEL_QUARTIC = 1 };
+
+/* Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16,
+ * kernel SPHV_KERNEL_CUBIC. */
 int32_t sphv_params_init(sphv_params* p, const double lo[3], const double len[3],
                          const int32_t grid[3], const int32_t periodic[3]);
 

@@ -96,7 +96,8 @@ bool finite_params(const sphv_params* p)
             !(p->cell[d] > 0.0) || !(p->inv_cell[d] > 0.0))
             return false;
     return std::isfinite(p->gamma) && p->gamma > 1.0 && p->eta > 0.0 && p->cfl > 0.0 &&
-           p->h_tol >= 0.0 && p->headroom >= 1.0 && p->max_iter >= 1 && p->max_iter <= 64;
+           p->h_tol >= 0.0 && p->headroom >= 1.0 && p->max_iter >= 1 && p->max_iter <= 64 &&
+           (p->kernel == SPHV_KERNEL_CUBIC || p->kernel == SPHV_KERNEL_QUARTIC);
 }
 
 Geom geom_of(const sphv_params* p)
@@ -720,7 +721,7 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     a.reach = c->dev.reach_d;
     a.qhead = META_QHEAD_D;
     return hip_status(launch_density(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
-                                     (int)v->layout.masked, (hipStream_t)stream));
+                                     (int)v->layout.masked, p->kernel, (hipStream_t)stream));
 }
 
 int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, void* state, void* stream)
@@ -744,7 +745,7 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     const FieldRef hrec = ref_rec(v->aos, v->plan[v->role_field[SPHV_H]].f);
     hipError_t e = launch_force_reach(c->dev, hrec, v->desc.stride, a.g, (DevState*)state, st);
     if (e != hipSuccess) return SPHV_E_HIP;
-    return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, st));
+    return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, p->kernel, st));
 }
 
 int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* stream)

@@ -144,8 +144,8 @@ hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const
                          hipStream_t s);
 hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
                           const Access& dst_acc, int64_t n, hipStream_t s);
-hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s);
-hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s);
+hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
+hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
                                const Access& outacc, int out_direct, DevState* st, double cfl, int64_t n,
                                double* partials, hipStream_t s);

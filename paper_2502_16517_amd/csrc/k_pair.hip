@@ -80,28 +80,51 @@ __device__ __forceinline__ void neumaier(float& s, float& c, float x)
     s = t;
 }
 
-// Cubic M4 spline in its truncated-power form, branch free:
+// The smoothing kernels in truncated-power form, branch free; W = w(q)/(pi h^3).
+// Cubic M4:
 //   w(q)  = (2-q)_+^3 / 4 - (1-q)_+^3      (= 1 - 1.5 q^2 + 0.75 q^3 below 1)
 //   w'(q) = 3 (1-q)_+^2 - 0.75 (2-q)_+^2
-// Both vanish identically for q >= 2, so no select is needed at the support
-// edge and the two pieces never diverge inside a wave.
-template <class R>
+// Quartic M5 (Sec. 2.1), scaled to the same support 2h (its knots at q = 0.4,
+// 1.2, 2), k = 1.25^4 / 10.24 = 15625/65536:
+//   w(q)  = k ((2-q)_+^4 - 5 (1.2-q)_+^4 + 10 (0.4-q)_+^4)
+//   w'(q) = -4 k ((2-q)_+^3 - 5 (1.2-q)_+^3 + 10 (0.4-q)_+^3)
+// All pieces vanish identically for q >= 2, so no select is needed at the
+// support edge and the pieces never diverge inside a wave.
+template <int KERN, class R>
 __device__ __forceinline__ void spline(R q, R& w, R& dw)
 {
     const R a = fmax(R(2) - q, R(0));
-    const R b = fmax(R(1) - q, R(0));
-    const R a2 = a * a;
-    const R b2 = b * b;
-    w = fma(R(0.25) * a2, a, -(b2 * b));
-    dw = fma(R(3), b2, R(-0.75) * a2);
+    if constexpr (KERN == SPHV_KERNEL_QUARTIC) {
+        const R b = fmax(R(1.2) - q, R(0));
+        const R c = fmax(R(0.4) - q, R(0));
+        const R a3 = a * a * a;
+        const R b3 = b * b * b;
+        const R c3 = c * c * c;
+        const R k = R(15625.0 / 65536.0);
+        w = k * fma(a3, a, fma(R(-5) * b3, b, R(10) * c3 * c));
+        dw = (R(-4) * k) * fma(R(-5), b3, fma(R(10), c3, a3));
+    } else {
+        const R b = fmax(R(1) - q, R(0));
+        const R a2 = a * a;
+        const R b2 = b * b;
+        w = fma(R(0.25) * a2, a, -(b2 * b));
+        dw = fma(R(3), b2, R(-0.75) * a2);
+    }
 }
 
-template <class R>
+template <int KERN, class R>
 __device__ __forceinline__ R spline_dw(R q)
 {
     const R a = fmax(R(2) - q, R(0));
-    const R b = fmax(R(1) - q, R(0));
-    return fma(R(3), b * b, R(-0.75) * (a * a));
+    if constexpr (KERN == SPHV_KERNEL_QUARTIC) {
+        const R b = fmax(R(1.2) - q, R(0));
+        const R c = fmax(R(0.4) - q, R(0));
+        const R k = R(15625.0 / 65536.0);
+        return (R(-4) * k) * fma(R(-5), b * b * b, fma(R(10), c * c * c, a * a * a));
+    } else {
+        const R b = fmax(R(1) - q, R(0));
+        return fma(R(3), b * b, R(-0.75) * (a * a));
+    }
 }
 
 // 1/sqrt(x) for normal x > 0: the hardware estimate refined by Newton-Raphson
@@ -527,7 +550,7 @@ __device__ __forceinline__ void lane_mask2(const R* sx, const R* sy, const R* sz
     }
 }
 
-template <bool DIRECT, bool FP32, bool MASKED>
+template <bool DIRECT, bool FP32, bool MASKED, int KERN>
 __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
 {
     using R = typename std::conditional<FP32, float, double>::type;
@@ -741,7 +764,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
                 const R rr = r2 * rsqrt_nr(fmax(r2, Tiny<R>::v));
                 const R q = rr * hin;
                 R w, dw;
-                spline(q, w, dw);
+                spline<KERN>(q, w, dw);
                 w = in ? w : (R)0;
                 dw = in ? dw : (R)0;
                 p0 = fma(m, w, p0);
@@ -959,7 +982,7 @@ __global__ __launch_bounds__(kWave) void k_density(PairArgs a)
 
 // ================================================================== force
 
-template <bool DIRECT, bool FP32, bool MASKED>
+template <bool DIRECT, bool FP32, bool MASKED, int KERN>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_force(PairArgs a)
 {
     using R = typename std::conditional<FP32, float, double>::type;
@@ -1135,8 +1158,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         auto term = [&](int t, R dx, R dy, R dz, R r2, bool live, R& pax, R& pay, R& paz, R& pdu) {
             const R y = rsqrt_nr(live ? r2 : (R)1);
             const R r = r2 * y;
-            const R gi = spline_dw(r * hinvi) * normi;
-            const R gj = spline_dw(r * shinv[t]) * snorm[t];
+            const R gi = spline_dw<KERN>(r * hinvi) * normi;
+            const R gj = spline_dw<KERN>(r * shinv[t]) * snorm[t];
             const R gbar = (R)0.5 * (gi + gj);
             const R ex = dx * y, ey = dy * y, ez = dz * y;
             const R w = (vxi - svx[t]) * ex + (vyi - svy[t]) * ey + (vzi - svz[t]) * ez;
@@ -1512,8 +1535,12 @@ hipError_t launch_pair(K kernel, std::atomic<int>& cache, const PairArgs& a0, in
 
 #define SPHV_PAIR_CASE(KERNEL, D, F, M, DENS)                                     \
     do {                                                                          \
+        if (kern == SPHV_KERNEL_QUARTIC) {                                        \
+            static std::atomic<int> cache_q{0};                                   \
+            return launch_pair(KERNEL<D, F, M, SPHV_KERNEL_QUARTIC>, cache_q, a, DENS, s); \
+        }                                                                         \
         static std::atomic<int> cache{0};                                         \
-        return launch_pair(KERNEL<D, F, M>, cache, a, DENS, s);                    \
+        return launch_pair(KERNEL<D, F, M, SPHV_KERNEL_CUBIC>, cache, a, DENS, s); \
     } while (0)
 
 #define SPHV_PAIR_DISPATCH(KERNEL, DENS)                                          \
@@ -1534,12 +1561,12 @@ hipError_t launch_pair(K kernel, std::atomic<int>& cache, const PairArgs& a0, in
         SPHV_PAIR_CASE(KERNEL, false, false, false, DENS);                        \
     } while (0)
 
-hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
+hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, int kern, hipStream_t s)
 {
     SPHV_PAIR_DISPATCH(k_density, 1);
 }
 
-hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, hipStream_t s)
+hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int kern, hipStream_t s)
 {
     SPHV_PAIR_DISPATCH(k_force, 0);
 }

@@ -26,6 +26,7 @@ F64, F32, I64, I32 = 1, 2, 3, 4
 IN, OUT, INOUT = 1, 2, 3
 LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT, LAYOUT_SORTED = 0, 1, 2, 3
 PREC_FP64, PREC_FP32 = 0, 1
+KERNEL_CUBIC, KERNEL_QUARTIC = 0, 1
 LOOP_DENSITY, LOOP_FORCE = 0, 1
 
 ROLES = ["user", "x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "ax", "ay", "az", "m", "h", "rho",
@@ -57,7 +58,7 @@ class Params(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3), ("cell", C.c_double * 3),
                 ("inv_cell", C.c_double * 3), ("grid", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
                 ("gamma", C.c_double), ("eta", C.c_double), ("cfl", C.c_double), ("h_tol", C.c_double),
-                ("headroom", C.c_double), ("max_iter", C.c_int32), ("reserved", C.c_int32)]
+                ("headroom", C.c_double), ("max_iter", C.c_int32), ("kernel", C.c_int32)]
 
 
 class State(C.Structure):
@@ -583,7 +584,7 @@ class Stepper:
         cells_destroy(self.cells)
         self.cells = None
         q = params_init(tuple(self.p.lo), tuple(self.p.len), tuple(int(g) for g in grid), tuple(self.p.periodic))
-        for name in ("gamma", "eta", "cfl", "h_tol", "headroom", "max_iter"):
+        for name in ("gamma", "eta", "cfl", "h_tol", "headroom", "max_iter", "kernel"):
             setattr(q, name, getattr(self.p, name))
         self.p = q
         self._make_cells()

@@ -55,17 +55,17 @@ def run_density_force(w, precision=sv.PREC_FP64, lay=None, tol=None, rec=None, *
     return after_density, out, state
 
 
-def oracle_density(orc, w, rec=None, targets=None, tol=1e-13):
+def oracle_density(orc, w, rec=None, targets=None, tol=1e-13, kernel=0):
     r = w.rec if rec is None else rec
     c = cols(r)
     return orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box(orc, w), w.eta, tol=tol, max_iter=16,
-                       targets=targets)
+                       targets=targets, kernel=kernel)
 
 
-def oracle_force(orc, w, rec, targets=None):
+def oracle_force(orc, w, rec, targets=None, kernel=0):
     c = cols(rec)
     return orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], c["h"], c["rho"], c["omega"],
-                     c["u"], c["alpha"], box(orc, w), inputs.GAMMA, targets=targets)
+                     c["u"], c["alpha"], box(orc, w), inputs.GAMMA, targets=targets, kernel=kernel)
 
 
 def rel(a, b):

@@ -53,6 +53,18 @@ def test_params_init():
         sv.params_init((0, 0, 0), (0.0, 1.0, 1.0), (4, 4, 4), (1, 1, 1))
 
 
+def test_kernel_choice_is_validated():
+    p = sv.params_init((0, 0, 0), (1.0, 1.0, 1.0), (8, 8, 8), (1, 1, 1))
+    assert p.kernel == sv.KERNEL_CUBIC
+    base = sv.cells_workspace_bytes(100, p)
+    assert base > 0
+    p.kernel = sv.KERNEL_QUARTIC
+    assert sv.cells_workspace_bytes(100, p) == base
+    for bad in (2, -1):
+        p.kernel = bad
+        assert sv.cells_workspace_bytes(100, p) == 0
+
+
 def _ws_bytes(fields, n=100, stride=256, l=None, prec=sv.PREC_FP64):
     d = sv.descriptor(fields, stride)
     return sv.view_workspace_bytes(d, n, l or sv.layout(), prec)
