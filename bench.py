@@ -116,8 +116,9 @@ PKW = {}
 KERNELS = {"cubic": 0, "quartic": 1}
 
 
-def make_stepper(torch, sv, inputs, w, precision, tuned=None):
-    """A Stepper on the workload; tuned = (grid, density layout, force layout)."""
+def make_stepper(torch, sv, inputs, w, precision, tuned=None, merged=False):
+    """A Stepper on the workload; tuned = (grid, density layout, force layout);
+    merged: one view over both loops with the density layout."""
     grid, ld, lf = tuned if tuned else (tuple(w.grid), sv.layout(), sv.layout())
     p = sv.params_init(w.lo, w.length, grid, w.periodic)
     p.eta = w.eta
@@ -126,7 +127,7 @@ def make_stepper(torch, sv, inputs, w, precision, tuned=None):
     if precision == sv.PREC_FP32:
         p.h_tol = 1e-6
     st = sv.Stepper(w.rec, p, precision, layout_density=ld, layout_force=lf,
-                    stream=torch.cuda.current_stream())
+                    stream=torch.cuda.current_stream(), merged=merged)
     return st
 
 
@@ -222,9 +223,11 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         e["d_gathered"].record(s)
         sv.sph_density(st.v_dens, st.cells, st.p, st.state, s)
         e["d_loop"].record(s)
-        sv.soa_to_aos(st.v_dens, s)
+        if not st.merged:              # one view over both loops: no scatter and gather between
+            sv.soa_to_aos(st.v_dens, s)
         e["d_scattered"].record(s)
-        sv.aos_to_soa(st.v_force, st.cells, s)
+        if not st.merged:
+            sv.aos_to_soa(st.v_force, st.cells, s)
         e["f_gathered"].record(s)
         sv.sph_force(st.v_force, st.cells, st.p, st.state, s)
         e["f_loop"].record(s)
@@ -335,6 +338,8 @@ def main():
     ap.add_argument("--kernel", default="cubic", choices=list(KERNELS),
                     help="smoothing kernel of the measured step: the cubic M4 spline, or the quartic M5 the "
                          "paper employs")
+    ap.add_argument("--no-merged", action="store_true",
+                    help="skip the extra timing of one view over both loops (the tuned layouts that are views)")
     ap.add_argument("--no-other-kernel", action="store_true",
                     help="skip the extra timing of the other smoothing kernel with the same layouts")
     ap.add_argument("--workload", default="tube64", choices=list(WORKLOADS),
@@ -404,6 +409,27 @@ def main():
     st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, t64)
     g64 = run_timed(torch, sv, st, args.steps, args.warmup, graph=True)
     st.close()
+
+    merged = None
+    if not args.no_merged:
+        # one view over both loops, with each tuned layout that is a view
+        cands = []
+        for lay in (t64[1], t64[2]):
+            if lay.kind in (sv.LAYOUT_DIRECT, sv.LAYOUT_SORTED):
+                continue
+            if not any(sv.layout_name(lay) == sv.layout_name(c) for c in cands):
+                cands.append(lay)
+        for lay in cands:
+            log(f"[bench] fp64 eager, one view over both loops, {sv.layout_name(lay)}")
+            st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, (t64[0], lay, lay), merged=True)
+            rm = run_timed(torch, sv, st, args.steps, args.warmup)
+            st.close()
+            rec = {"layout": sv.layout_name(lay), "value": rm["pairs"] / (rm["ms_total"] / 1e3),
+                   "ms_per_step": rm["ms_total"] / args.steps, "ms_span": rm["ms_span"],
+                   "ms_gather": rm["ms_density_gather"], "ms_scatter": rm["ms_force_scatter"],
+                   "ms_density": rm["ms_density"], "ms_force": rm["ms_force"], "flags": rm["flags"]}
+            if merged is None or rec["value"] > merged["value"]:
+                merged = rec
 
     other = None
     if not args.no_other_kernel:
@@ -502,6 +528,8 @@ def main():
         "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
         "other_kernel": other,
+        # one view over both loops (gather before density, scatter after the reduction)
+        "merged_view": merged,
         "conversions": conv,
         "reduce_ms": r64["ms_reduce"],
         "hbm_frac_step": None,

@@ -312,7 +312,7 @@ void sphv_view_destroy(sphv_view* v);
  * perm.  View members: IN x, y, z, m; INOUT h; OUT rho, omega, wcount.
  * For each particle i, at its current h, over j in its cells' window:
  *   rho_i = sum_j m_j W(r_ij, h), drho_i/dh = sum_j m_j dW/dh, n_i = sum_j W
- * (j = i included), W the cubic M4 spline with support 2h; then a Newton step
+ * (j = i included), W the kernel p->kernel selects (support 2h); then a Newton step
  * on rho_i(h) h^3 = m_i eta^3, h+ = h - f/f', f' = drho/dh + 3 m eta^3/h^4,
  * clamped to [h/2, 2h] and to the cell cap (fixed point eta (m/rho)^(1/3) if
  * f' <= 0).  The current h is accepted when |h+ - h| <= h_tol h, else h = h+
@@ -328,7 +328,13 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
  *   mu = min(w, 0), v_sig,ij = c_i + c_j - 3 mu,
  *   Pi = -(alpha_i + alpha_j)/4 v_sig,ij mu / ((rho_i + rho_j)/2),
  *   a_i  -= m_j (A_i g_i + A_j g_j + Pi gbar) r_hat
- *   u_dt += m_j (A_i g_i + Pi gbar / 2) w,   v_sig,i = max(2 c_i, max_j v_sig,ij). */
+ *   u_dt += m_j (A_i g_i + Pi gbar / 2) w,   v_sig,i = max(2 c_i, max_j v_sig,ij).
+ * One view may serve both loops (the union of their members, h, rho and omega
+ * INOUT): the force loop then reads the density's results inside the view,
+ * and its windows take h from the view.  FP32 views must hold the twelve IN
+ * members as members the view only reads (stored as floats); a view that
+ * also writes one of them fails with SPHV_E_DESCRIPTOR (likewise x, y, z, m
+ * for the density loop). */
 int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p,
                        void* state_dev, void* stream);
 /* Time-step reduction over an open force view after sphv_sph_force: in one
@@ -336,7 +342,8 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p,
  * division rounded per particle) and the conservation sums of sphv_state.
  * Updates the state block: t += old dt, dt_prev = old dt, dt = new dt,
  * nstep += 1.  Inputs m, v, u, h are read from the records (members a view
- * only reads are never modified while it is open), outputs from the view. */
+ * only reads are never modified while it is open), outputs from the view; h
+ * from the view when the view writes it (one view over both loops). */
 int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state_dev, void* stream);
 
 /* Kick / drift / kick with prediction (paper Sec. 2.1 steps 3-5) on the records

@@ -658,8 +658,10 @@ void sphv_view_destroy(sphv_view* v)
 
 namespace {
 
+// nstaged: the first roles_in that the loop stages for its neighbours; an FP32
+// loop reads those from a view as stored floats
 int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void* state,
-                   const int* roles_in, int nin, const int* roles_out, int nout, PairArgs* a)
+                   const int* roles_in, int nin, int nstaged, const int* roles_out, int nout, PairArgs* a)
 {
     if (!v || !c || !p || !state) return SPHV_E_INVALID_ARG;
     if (!finite_params(p)) return SPHV_E_INVALID_ARG;
@@ -667,8 +669,14 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     if (!c->built || c->dev.n != v->n || v->index != c->dev.perm) return SPHV_E_STATE;
     for (int k = 0; k < nin; ++k) if (int32_t s = need(v, roles_in[k], SPHV_IN)) return s;
     for (int k = 0; k < nout; ++k) if (int32_t s = need(v, roles_out[k], SPHV_OUT)) return s;
-    std::memset(a, 0, sizeof(*a));
     bool direct = is_direct(v->layout.kind);
+    // an FP32 view stores a member as a float only when the loop only reads it
+    // (the gather's rounding); a member it also writes stays a double, which
+    // the FP32 loops cannot stage
+    if (v->precision == SPHV_PREC_FP32 && !direct)
+        for (int k = 0; k < nstaged; ++k)
+            if (v->plan[v->role_field[roles_in[k]]].view_dtype != SPHV_F32) return SPHV_E_DESCRIPTOR;
+    std::memset(a, 0, sizeof(*a));
     // a view over records stored cell by cell indexes them in storage order
     const bool sorted = v->layout.kind == SPHV_LAYOUT_SORTED;
     if (sorted && !c->sorted) return SPHV_E_STATE;
@@ -713,7 +721,7 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     const int in[] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_M, SPHV_H};
     const int out[] = {SPHV_H, SPHV_RHO, SPHV_OMEGA, SPHV_WCOUNT};
     PairArgs a;
-    int32_t s = pair_setup(v, c, p, state, in, 5, out, 4, &a);
+    int32_t s = pair_setup(v, c, p, state, in, 5, 4, out, 4, &a);
     if (s) return s;
     if (c->params.grid[0] != p->grid[0] || c->params.grid[1] != p->grid[1] || c->params.grid[2] != p->grid[2])
         return SPHV_E_INVALID_ARG;
@@ -730,7 +738,7 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
                       SPHV_RHO, SPHV_OMEGA, SPHV_U, SPHV_ALPHA};
     const int out[] = {SPHV_AX, SPHV_AY, SPHV_AZ, SPHV_UDT, SPHV_VSIG};
     PairArgs a;
-    int32_t s = pair_setup(v, c, p, state, in, 12, out, 5, &a);
+    int32_t s = pair_setup(v, c, p, state, in, 12, 12, out, 5, &a);
     if (s) return s;
     if (c->params.grid[0] != p->grid[0] || c->params.grid[1] != p->grid[1] || c->params.grid[2] != p->grid[2])
         return SPHV_E_INVALID_ARG;
@@ -740,10 +748,17 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     a.qhead = META_QHEAD_F;
     hipStream_t st = (hipStream_t)stream;
     bool direct = is_direct(v->layout.kind);
-    // windows from the converged h: members a view only reads are never
-    // modified while it is open, so the records hold them
-    const FieldRef hrec = ref_rec(v->aos, v->plan[v->role_field[SPHV_H]].f);
-    hipError_t e = launch_force_reach(c->dev, hrec, v->desc.stride, a.g, (DevState*)state, st);
+    // windows from the converged h: a member the view only reads is never
+    // modified while it is open, so the records hold it; a view that also
+    // writes h (one view over density and force) holds the density's h
+    const FieldPlan& hp = v->plan[v->role_field[SPHV_H]];
+    hipError_t e;
+    if (!direct && (hp.f.access & SPHV_OUT)) {
+        const Access va = acc_view(v);
+        e = launch_force_reach(c->dev, ref_view(v, hp), 0, &va, a.g, (DevState*)state, st);
+    } else {
+        e = launch_force_reach(c->dev, ref_rec(v->aos, hp.f), v->desc.stride, nullptr, a.g, (DevState*)state, st);
+    }
     if (e != hipSuccess) return SPHV_E_HIP;
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, p->kernel, st));
 }
@@ -759,7 +774,8 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
     for (int k = 0; k < 5; ++k) if (int32_t s = need(v, rout[k], SPHV_OUT)) return s;
     if (v->n == 0) return SPHV_OK;
     // inputs from the records (A_in members are never modified while the view
-    // is open), outputs from where the loop wrote them
+    // is open), outputs from where the loop wrote them; h from the view when
+    // the view also writes it (one view over density and force)
     const bool direct = is_direct(v->layout.kind);
     FieldRef in6[6], out5[5];
     for (int k = 0; k < 6; ++k) in6[k] = ref_rec(v->aos, v->plan[v->role_field[rin[k]]].f);
@@ -767,10 +783,13 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
         const FieldPlan& fp = v->plan[v->role_field[rout[k]]];
         out5[k] = direct ? ref_rec(v->aos, fp.f) : ref_view(v, fp);
     }
+    const FieldPlan& hp = v->plan[v->role_field[SPHV_H]];
+    const bool h_in_view = !direct && (hp.f.access & SPHV_OUT);
+    const FieldRef hv = h_in_view ? ref_view(v, hp) : in6[5];
     Access ra = acc_rec(v->index, v->desc.stride);
     Access oa = direct ? ra : acc_view(v);
-    return hip_status(launch_force_reduce(in6, ra, out5, oa, direct, (DevState*)state, p->cfl, v->n, v->red_part,
-                                          (hipStream_t)stream));
+    return hip_status(launch_force_reduce(in6, ra, out5, oa, direct, h_in_view ? &hv : nullptr, (DevState*)state,
+                                          p->cfl, v->n, v->red_part, (hipStream_t)stream));
 }
 
 // -------------------------------------------------------------- kick/drift

@@ -137,8 +137,10 @@ hipError_t launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_state_init(DevState* st, int full, hipStream_t s);
 hipError_t launch_cells_build(const CellsDev& c, const FieldRef* xyzh, const Access& rec,
                               const Geom& g, DevState* st, hipStream_t s);
-hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Geom& g, DevState* st,
-                              hipStream_t s);
+// h from the records (through perm, stride bytes apart), or from a view (view_acc
+// not null: element p of the view is sorted position p)
+hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Access* view_acc,
+                              const Geom& g, DevState* st, hipStream_t s);
 hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
                          const Access& dst_acc, const int32_t* cell_key, const Geom& g, int64_t n,
                          hipStream_t s);
@@ -146,9 +148,10 @@ hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, cons
                           const Access& dst_acc, int64_t n, hipStream_t s);
 hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
 hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
+// hview not null: h is read from there (with outacc) instead of in6[5]
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
-                               const Access& outacc, int out_direct, DevState* st, double cfl, int64_t n,
-                               double* partials, hipStream_t s);
+                               const Access& outacc, int out_direct, const FieldRef* hview, DevState* st,
+                               double cfl, int64_t n, double* partials, hipStream_t s);
 // whole records: dst[didx ? didx[p] : p] = src[sidx ? sidx[p] : p], stride bytes
 // each (stride and both bases multiples of 4 bytes)
 hipError_t launch_rec_move(const void* src, void* dst, const int32_t* sidx, const int32_t* didx,

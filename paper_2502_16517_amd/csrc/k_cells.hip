@@ -589,15 +589,20 @@ __global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, 
 // k_force_hbits folds 2 h of every particle into its cell (float bits rounded
 // up, as k_bin does); k_force_own turns them into R and a block maximum of R
 // into meta[rslot] (one atomic per block of 1024 cells).
+template <bool VIEW>
 __global__ void k_force_hbits(const int32_t* perm, const int32_t* key_sorted, FieldRef h, uint64_t stride,
-                              int64_t n, uint32_t* hbits)
+                              Access vacc, int64_t n, uint32_t* hbits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < n;
     int k = 0;
     uint32_t b = 0;
     if (valid) {
-        const double v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
+        double v;
+        if constexpr (VIEW)
+            v = ld_f64(h, locate<false>(vacc, p));
+        else
+            v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
         b = __float_as_uint(__double2float_ru(2.0 * v));
         k = key_sorted[p];
     }
@@ -753,15 +758,19 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
     return hipGetLastError();
 }
 
-hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Geom& g, DevState* st,
-                              hipStream_t s)
+hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Access* view_acc,
+                              const Geom& g, DevState* st, hipStream_t s)
 {
     // hmax_f and the largest own reach start at zero with cells_build and only
     // grow: a later force call on larger h widens the windows, never narrows them
     hipError_t e;
     if (c.n > 0) {
-        hipLaunchKernelGGL(k_force_hbits, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h, stride, c.n,
-                           c.hmax_f);
+        if (view_acc)
+            hipLaunchKernelGGL(k_force_hbits<true>, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h,
+                               stride, *view_acc, c.n, c.hmax_f);
+        else
+            hipLaunchKernelGGL(k_force_hbits<false>, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h,
+                               stride, Access{}, c.n, c.hmax_f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_f,

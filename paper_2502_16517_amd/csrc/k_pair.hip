@@ -1293,12 +1293,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
 struct RedArgs {
     FieldRef in[6];     // m vx vy vz u h   (records, through the index)
     FieldRef out[5];    // ax ay az u_dt v_sig (view or records)
+    FieldRef hview;     // h where the outputs are, when h_in_view
     Access rec;
     Access outacc;
     DevState* state;
     double* part;       // [nblocks][16]
     int64_t n;
     double cfl;
+    int32_t h_in_view;  // h was written into the view by an earlier loop on it
+    int32_t pad;
 };
 
 constexpr int kRedThreads = 256;
@@ -1318,7 +1321,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(RedArgs r)
         const Loc<DIRECT_OUT> lo = locate<DIRECT_OUT>(r.outacc, p);
         const double m = ld_f64(r.in[0], lr);
         const double vx = ld_f64(r.in[1], lr), vy = ld_f64(r.in[2], lr), vz = ld_f64(r.in[3], lr);
-        const double u = ld_f64(r.in[4], lr), h = ld_f64(r.in[5], lr);
+        const double u = ld_f64(r.in[4], lr);
+        const double h = r.h_in_view ? ld_f64(r.hview, lo) : ld_f64(r.in[5], lr);
         const double ax = ld_f64(r.out[0], lo), ay = ld_f64(r.out[1], lo), az = ld_f64(r.out[2], lo);
         const double du = ld_f64(r.out[3], lo), vs = ld_f64(r.out[4], lo);
         s[0] += m * vx;
@@ -1367,7 +1371,8 @@ __global__ __launch_bounds__(kStageThreads) void k_reduce_staged(RedArgs r, Stag
             const Loc<DIRECT_OUT> lo = locate<DIRECT_OUT>(r.outacc, p);
             const double m = ld_f64(r.in[0], lr);
             const double vx = ld_f64(r.in[1], lr), vy = ld_f64(r.in[2], lr), vz = ld_f64(r.in[3], lr);
-            const double u = ld_f64(r.in[4], lr), h = ld_f64(r.in[5], lr);
+            const double u = ld_f64(r.in[4], lr);
+            const double h = r.h_in_view ? ld_f64(r.hview, lo) : ld_f64(r.in[5], lr);
             const double ax = ld_f64(r.out[0], lo), ay = ld_f64(r.out[1], lo), az = ld_f64(r.out[2], lo);
             const double du = ld_f64(r.out[3], lo), vs = ld_f64(r.out[4], lo);
             s[0] += m * vx;
@@ -1572,12 +1577,15 @@ hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int
 }
 
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5, const Access& outacc,
-                               int out_direct, DevState* st, double cfl, int64_t n, double* partials,
-                               hipStream_t s)
+                               int out_direct, const FieldRef* hview, DevState* st, double cfl, int64_t n,
+                               double* partials, hipStream_t s)
 {
     RedArgs r;
     for (int k = 0; k < 6; ++k) r.in[k] = in6[k];
     for (int k = 0; k < 5; ++k) r.out[k] = out5[k];
+    r.h_in_view = hview ? 1 : 0;
+    r.pad = 0;
+    r.hview = hview ? *hview : in6[5];
     r.rec = rec;
     r.outacc = outacc;
     r.state = st;

@@ -209,6 +209,11 @@ KICK_FIELDS = [("x", INOUT), ("y", INOUT), ("z", INOUT), ("vx", INOUT), ("vy", I
                ("vhx", INOUT), ("vhy", INOUT), ("vhz", INOUT), ("ax", IN), ("ay", IN), ("az", IN),
                ("u", INOUT), ("uh", INOUT), ("u_dt", IN)]
 CELLS_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("h", IN)]
+# one view over density and force: the union of both loops' members; h, rho and
+# omega are written by the density loop and read by the force loop inside it
+MERGED_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("vx", IN), ("vy", IN), ("vz", IN), ("m", IN), ("h", INOUT),
+                 ("rho", INOUT), ("omega", INOUT), ("wcount", OUT), ("u", IN), ("alpha", IN), ("ax", OUT),
+                 ("ay", OUT), ("az", OUT), ("u_dt", OUT), ("v_sig", OUT)]
 
 
 def density_descriptor():
@@ -225,6 +230,10 @@ def kick_descriptor():
 
 def cells_descriptor():
     return descriptor(_rec_fields(CELLS_FIELDS))
+
+
+def merged_descriptor():
+    return descriptor(_rec_fields(MERGED_FIELDS))
 
 
 def soa_descriptor(spec, n: int, base_slots=None):
@@ -474,19 +483,25 @@ class Stepper:
     into cell order after each cells_build).  sort_records: move the records
     into cell order after each cells_build (implied by a SORTED layout).  aos
     may be an (n*256,) uint8 device tensor holding 256-byte records, or None to
-    upload ``rec``.
+    upload ``rec``.  merged: one view over both loops (MERGED_FIELDS, FP64,
+    layout_density), gathered before the density loop and scattered after the
+    force loop, so the density's outputs never leave the view in between.
     """
 
     def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
                  layout_density: Layout | None = None, layout_force: Layout | None = None,
-                 device="cuda", aos=None, stream=None, sort_records: bool = False):
+                 device="cuda", aos=None, stream=None, sort_records: bool = False, merged: bool = False):
         import torch
         self.torch = torch
         self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
         self.p = params
         self.precision = precision
+        self.merged = merged
+        if merged and precision != PREC_FP64:
+            raise ValueError("a merged view is FP64: the FP32 force loop stages its members as floats, which a "
+                             "view stores only for members it does not write")
         self.ld = layout_density or layout()
-        self.lf = layout_force or layout()
+        self.lf = self.ld if merged else (layout_force or layout())
         self.sort_always = sort_records
         self.sort_ws = None
         self.stream = stream
@@ -500,6 +515,7 @@ class Stepper:
         self.d_dens = density_descriptor()
         self.d_force = force_descriptor()
         self.d_kick = kick_descriptor()
+        self.d_merged = merged_descriptor()
         self.v_dens = self.v_force = self.cells = None
         self._make_cells()
         self.set_layouts(self.ld, self.lf)
@@ -531,10 +547,12 @@ class Stepper:
     def density(self):
         aos_to_soa(self.v_dens, self.cells, self.stream)
         sph_density(self.v_dens, self.cells, self.p, self.state, self.stream)
-        soa_to_aos(self.v_dens, self.stream)
+        if not self.merged:
+            soa_to_aos(self.v_dens, self.stream)
 
     def force(self):
-        aos_to_soa(self.v_force, self.cells, self.stream)
+        if not self.merged:
+            aos_to_soa(self.v_force, self.cells, self.stream)
         sph_force(self.v_force, self.cells, self.p, self.state, self.stream)
         step_reduce(self.v_force, self.p, self.state, self.stream)
         soa_to_aos(self.v_force, self.stream)
@@ -554,6 +572,18 @@ class Stepper:
     def set_layouts(self, layout_density: Layout | None = None, layout_force: Layout | None = None):
         """Re-plans the views (no view may be open)."""
         u8 = dict(dtype=self.torch.uint8, device=self.device)
+        if self.merged:
+            lay = layout_density or layout_force
+            if lay is not None:
+                self._destroy_views()
+                self.ld = self.lf = lay
+                self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_merged, self.n, lay,
+                                                                              self.precision)), **u8)
+                self.v_dens = self.v_force = view_create(self.d_merged, self.n, lay, self.precision, self.aos,
+                                                         self.perm_ptr, self.ws_dens)
+            if self.sorting:
+                self._sort_workspace()
+            return
         if layout_density is not None:
             if self.v_dens:
                 view_destroy(self.v_dens)
@@ -577,10 +607,7 @@ class Stepper:
 
     def set_grid(self, grid):
         """Re-plans cells and views for another grid (no view may be open)."""
-        for v in (self.v_dens, self.v_force):
-            if v:
-                view_destroy(v)
-        self.v_dens = self.v_force = None
+        self._destroy_views()
         cells_destroy(self.cells)
         self.cells = None
         q = params_init(tuple(self.p.lo), tuple(self.p.len), tuple(int(g) for g in grid), tuple(self.p.periodic))
@@ -605,7 +632,10 @@ class Stepper:
         The density layout is chosen first; the force layouts are then timed
         after one density pass with it (the records hold that pass's results
         afterwards).  Returns {"density": (best, table), "force": ...,
-        ["grid": ...]}."""
+        ["grid": ...]}.  Not for a merged view (the tuner times each loop on a
+        view of its own)."""
+        if self.merged:
+            raise ValueError("autotune times each loop on its own view; use set_layouts on a merged Stepper")
         out = {}
         if cells_per_support:
             if h_ref is None:
@@ -671,10 +701,16 @@ class Stepper:
         return (view_i32(info.perm, self.n), view_i32(info.cell_start, nc + 1), view_i32(info.key, self.n),
                 view_i32(info.reach, 2 * nc))
 
+    def _destroy_views(self):
+        vd, vf = getattr(self, "v_dens", None), getattr(self, "v_force", None)
+        if vd:
+            view_destroy(vd)
+        if vf and vf is not vd:
+            view_destroy(vf)
+        self.v_dens = self.v_force = None
+
     def close(self):
-        for v in (getattr(self, "v_dens", None), getattr(self, "v_force", None)):
-            if v:
-                view_destroy(v)
+        self._destroy_views()
         if getattr(self, "cells", None):
             cells_destroy(self.cells)
         self.v_dens = self.v_force = self.cells = None
