@@ -209,17 +209,19 @@ def test_ragged_sizes_step_matches_oracle(orc, drop):
     assert np.array_equal(bits(ref), bits(after))
 
 
-def test_degenerate_sizes(orc):
+@pytest.mark.parametrize("merged", [False, True])
+def test_degenerate_sizes(orc, merged):
     """No particles: every call of a step succeeds and leaves nothing behind.
     One particle: no pairs, so zero acceleration and heating and v_sig = 2 c;
     its own kernel term alone cannot reach the density target, so h grows
-    until the cell cap stops it, which the status flags report."""
+    until the cell cap stops it, which the status flags report.  Also with one
+    view over both loops."""
     w0 = inputs.config1()
     import dataclasses
     for n in (0, 1):
         w = dataclasses.replace(w0, rec=np.ascontiguousarray(w0.rec[:n]))
-        print(f"[degenerate] n={n}", flush=True)
-        st = sv.Stepper(w.rec, sv.params_for(w))
+        print(f"[degenerate] n={n} merged={merged}", flush=True)
+        st = sv.Stepper(w.rec, sv.params_for(w), merged=merged)
         st.step()
         out = st.records()
         state = st.read_state()
