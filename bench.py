@@ -112,13 +112,15 @@ WORKLOADS = {
     "kh256": ("config5", {}, "Kelvin-Helmholtz shear layer 256^3 = 16,777,216 particles, periodic unit box"),
 }
 PKW = {}
+HOST_RECORDS = False
 # smoothing kernels (the library's kernel ids)
 KERNELS = {"cubic": 0, "quartic": 1}
 
 
 def make_stepper(torch, sv, inputs, w, precision, tuned=None, merged=False):
     """A Stepper on the workload; tuned = (grid, density layout, force layout);
-    merged: one view over both loops with the density layout."""
+    merged: one view over both loops with the density layout.  With
+    HOST_RECORDS the records live in pinned host memory."""
     grid, ld, lf = tuned if tuned else (tuple(w.grid), sv.layout(), sv.layout())
     p = sv.params_init(w.lo, w.length, grid, w.periodic)
     p.eta = w.eta
@@ -126,8 +128,12 @@ def make_stepper(torch, sv, inputs, w, precision, tuned=None, merged=False):
         setattr(p, k, v)
     if precision == sv.PREC_FP32:
         p.h_tol = 1e-6
+    aos = None
+    if HOST_RECORDS:
+        import numpy as np
+        aos = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(w.rec))).pin_memory()
     st = sv.Stepper(w.rec, p, precision, layout_density=ld, layout_force=lf,
-                    stream=torch.cuda.current_stream(), merged=merged)
+                    stream=torch.cuda.current_stream(), merged=merged, aos=aos)
     return st
 
 
@@ -328,6 +334,36 @@ def cpu_baseline(inputs, w, kernel=0, reps=3):
             "pairs": pairs}
 
 
+def host_records(torch, sv, inputs, w, desc, args):
+    """The step with the records in pinned host memory: views (gathered once
+    per loop) against loops on the records (every candidate fetched across
+    the host link).  One JSON line; its value is host-link inclusive."""
+    global HOST_RECORDS
+    HOST_RECORDS = True
+    lays = args.layouts.split(",") if args.layouts else ["soa/tpiauto/branch", "soa/tpiauto/branch"]
+    runs = {}
+    for name, names in (("views", lays), ("records", ["direct/tpiauto/branch", "direct/tpiauto/branch"])):
+        log(f"[bench] host records, {name}: {names}")
+        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, (tuple(w.grid), layout_of(sv, names[0]),
+                                                                layout_of(sv, names[1])))
+        r = run_timed(torch, sv, st, args.steps, args.warmup)
+        st.close()
+        runs[name] = {"layouts": names, "ms_per_step": r["ms_total"] / args.steps,
+                      "value": r["pairs"] / (r["ms_total"] / 1e3), "ms_density": r["ms_density"],
+                      "ms_force": r["ms_force"], "ms_density_gather": r["ms_density_gather"],
+                      "ms_force_gather": r["ms_force_gather"], "ms_kick_drift": r["ms_kick_drift"],
+                      "flags": r["flags"]}
+    out = {"metric": "pair interactions/s (density+force incl. AoS<->SoA views), records in pinned host memory",
+           "value": runs["views"]["value"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": runs["views"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": desc + ", 256-byte 32-slot records in pinned host memory, FP64", "n": w.n,
+                      "records": "pinned host"},
+           "host_records": runs,
+           "views_speedup": runs["records"]["ms_per_step"] / runs["views"]["ms_per_step"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +374,10 @@ def main():
     ap.add_argument("--kernel", default="cubic", choices=list(KERNELS),
                     help="smoothing kernel of the measured step: the cubic M4 spline, or the quartic M5 the "
                          "paper employs")
+    ap.add_argument("--host-records", action="store_true",
+                    help="records in pinned host memory (every record access crosses the host link): the step "
+                         "with the views of --layouts (SoA without it) and with loops on the records; not the "
+                         "headline, whose records are resident in HBM")
     ap.add_argument("--no-merged", action="store_true",
                     help="skip the extra timing of one view over both loops (the tuned layouts that are views)")
     ap.add_argument("--no-other-kernel", action="store_true",
@@ -388,6 +428,9 @@ def main():
     PKW["kernel"] = KERNELS[args.kernel]
     log(f"[bench] generating the workload: {desc}")
     w = getattr(inputs, gen)()
+    if args.host_records:
+        host_records(torch, sv, inputs, w, desc, args)
+        return
     if args.layouts:
         names = args.layouts.split(",")
         t64 = (tuple(w.grid), layout_of(sv, names[0]), layout_of(sv, names[1]))

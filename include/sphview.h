@@ -31,6 +31,14 @@
  *    owns them (AoS, workspaces, state block) and keeps them alive while any
  *    handle or queued work uses them.  The library never allocates or frees
  *    device memory; it allocates only small host handles freed by *_destroy.
+ *  - The records (aos_dev) may also be managed memory or pinned host memory
+ *    that the device maps at the same address (hipHostMalloc): every record
+ *    access then crosses the host link, which the views limit to one per
+ *    member per loop (Sec. 7.5 compares such placements).  A call that is
+ *    about to enqueue work on records checks their first and last bytes with
+ *    hipPointerGetAttributes and fails with SPHV_E_INVALID_ARG, before
+ *    enqueuing anything, on memory the device cannot address (pageable
+ *    host memory); a view is checked at its first gather or loop call.
  *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work is enqueued asynchronously on it; only sphv_read_state and
  *    sphv_write_state synchronise with the host.

@@ -138,6 +138,7 @@ struct FieldPlan {
 };
 
 struct sphv_view {
+    bool records_ok = false;          // the records' addresses passed check_records
     std::vector<sphv_field> fields;   // own copy of the caller's descriptor fields
     std::vector<FieldPlan> plan;
     int role_field[SPHV_NROLES];
@@ -346,6 +347,15 @@ int32_t check_layout(const sphv_layout* l, int32_t precision)
 }
 
 // role requirements: readable (IN bit) or writable (OUT bit), f64 in the records
+// The view's records are addressable by the device (checked once per view).
+int32_t records_ok(sphv_view* v)
+{
+    if (v->records_ok) return SPHV_OK;
+    if (int32_t r = check_records(v->aos, &v->desc, v->n)) return r;
+    v->records_ok = true;
+    return SPHV_OK;
+}
+
 int32_t need(const sphv_view* v, int role, uint16_t bits)
 {
     int k = v->role_field[role];
@@ -470,6 +480,7 @@ int32_t sphv_cells_build(sphv_cells* c, const void* aos, const sphv_descriptor* 
     int rf[SPHV_NROLES];
     int32_t st = check_descriptor(d, c->dev.n, rf);
     if (st) return st;
+    if ((st = check_records(aos, d, c->dev.n))) return st;
     const int roles[4] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_H};
     FieldRef f[4];
     for (int k = 0; k < 4; ++k) {
@@ -498,7 +509,14 @@ int32_t sphv_records_sort(sphv_cells* c, void* aos, uint32_t stride, void* ws, s
     if (n > 0 && !aos) return SPHV_E_INVALID_ARG;
     if (!ws || (uintptr_t)ws % kAlign || ws_bytes < sphv_records_sort_workspace_bytes(stride, n))
         return SPHV_E_WORKSPACE;
+
     if (!c->built) return SPHV_E_STATE;
+    {
+        // whole records: from aos to the last byte of record n-1
+        const sphv_field last{stride - 4u, SPHV_ROLE_USER, SPHV_I32, SPHV_INOUT};
+        const sphv_descriptor dl{stride, 1, 0, &last};
+        if (int32_t r = check_records(aos, &dl, n)) return r;
+    }
     hipStream_t s = (hipStream_t)stream;
     // sorted copy in the workspace, then back over the records in storage order
     if (launch_rec_move(aos, ws, c->dev.perm, nullptr, stride, n, s) != hipSuccess) return SPHV_E_HIP;
@@ -591,6 +609,10 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     for (const FieldPlan& p : v->plan) needs_cells |= p.rel_axis >= 0;
     if (needs_cells && (!cells || !cells->built || cells->dev.n != v->n || v->index != cells->dev.perm))
         return SPHV_E_STATE;
+    // the gather reads the records: checked once per view, before its first
+    // gather (a view on the records is checked by the first loop call instead)
+    if (!is_direct(v->layout.kind))
+        if (int32_t r = records_ok(v)) return r;
     if (!is_direct(v->layout.kind)) {
         std::lock_guard<std::mutex> lk(g_open_mutex);
         for (sphv_view* o : g_open)
@@ -676,6 +698,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     if (v->precision == SPHV_PREC_FP32 && !direct)
         for (int k = 0; k < nstaged; ++k)
             if (v->plan[v->role_field[roles_in[k]]].view_dtype != SPHV_F32) return SPHV_E_DESCRIPTOR;
+    if (int32_t r = records_ok(v)) return r;
     std::memset(a, 0, sizeof(*a));
     // a view over records stored cell by cell indexes them in storage order
     const bool sorted = v->layout.kind == SPHV_LAYOUT_SORTED;
@@ -772,6 +795,7 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
     const int rout[5] = {SPHV_AX, SPHV_AY, SPHV_AZ, SPHV_UDT, SPHV_VSIG};
     for (int k = 0; k < 6; ++k) if (int32_t s = need(v, rin[k], SPHV_IN)) return s;
     for (int k = 0; k < 5; ++k) if (int32_t s = need(v, rout[k], SPHV_OUT)) return s;
+    if (int32_t s = records_ok(v)) return s;
     if (v->n == 0) return SPHV_OK;
     // inputs from the records (A_in members are never modified while the view
     // is open), outputs from where the loop wrote them; h from the view when
@@ -802,6 +826,7 @@ int32_t sphv_kick_drift(void* aos, const sphv_descriptor* d, int64_t n, const sp
     int rf[SPHV_NROLES];
     int32_t s = check_descriptor(d, n, rf);
     if (s) return s;
+    if ((s = check_records(aos, d, n))) return s;
     const int roles[15] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_VHX, SPHV_VHY, SPHV_VHZ,
                            SPHV_AX, SPHV_AY, SPHV_AZ, SPHV_U, SPHV_UH, SPHV_UDT};
     FieldRef f[15];
@@ -862,6 +887,34 @@ void sphv_graph_destroy(sphv_graph* g)
 }  // extern "C"
 
 namespace sphv {
+namespace {
+// An address the kernels may dereference: device or managed memory, or pinned
+// host memory that the device maps at the same address (hipHostMalloc).
+// Pageable host memory is not mapped: a kernel reading it would fault.
+bool device_addressable(const void* p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return true;
+    return a.type == hipMemoryTypeHost && a.devicePointer == p;
+}
+}  // namespace
+
+int32_t check_records(const void* aos, const sphv_descriptor* d, int64_t n)
+{
+    if (n <= 0 || !d || !aos) return SPHV_OK;
+    uint64_t end = 0;
+    for (uint32_t k = 0; k < d->n_fields; ++k) {
+        const uint64_t e = d->fields[k].offset + (uint64_t)(n - 1) * d->stride + dtype_size(d->fields[k].dtype);
+        end = e > end ? e : end;
+    }
+    const char* b = (const char*)aos;
+    return device_addressable(b) && (end == 0 || device_addressable(b + end - 1)) ? SPHV_OK : SPHV_E_INVALID_ARG;
+}
+
 CellsDev* cells_dev(sphv_cells* c) { return &c->dev; }
 bool cells_sorted(const sphv_cells* c) { return c->sorted; }
 void cells_set_sorted(sphv_cells* c, bool sorted) { c->sorted = sorted; }

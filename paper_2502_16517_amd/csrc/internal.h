@@ -164,6 +164,10 @@ hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g
 int pair_grid_blocks(int64_t max_items);
 // the parts of a cells handle that the tuner saves and puts back around its
 // trials on records stored cell by cell (abi.cpp)
+// SPHV_OK when the device may address every member of records 0..n-1 of aos
+// (device, managed, or pinned host memory mapped at the same address), else
+// SPHV_E_INVALID_ARG; checked on the host before anything is enqueued
+int32_t check_records(const void* aos, const sphv_descriptor* d, int64_t n);
 CellsDev* cells_dev(sphv_cells* c);
 bool cells_sorted(const sphv_cells* c);
 void cells_set_sorted(sphv_cells* c, bool sorted);

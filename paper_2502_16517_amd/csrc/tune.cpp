@@ -256,6 +256,7 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
     if (!ws || (uintptr_t)ws % kAlignT || ws_bytes < need_b) return SPHV_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (int32_t c = refuse_capture(s)) return c;
+    if ((st = check_records(aos, d, n))) return st;
 
     // trials on sorted records move them, and the cells' perm and key, and put
     // all of it back before the next trial
@@ -385,6 +386,8 @@ int32_t sphv_autotune_grid(void* aos, const sphv_descriptor* d_density, const sp
     if (!ws || (uintptr_t)ws % kAlignT || ws_bytes < need_b) return SPHV_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (int32_t c = refuse_capture(s)) return c;
+    if (int32_t r = check_records(aos, d_density, n)) return r;
+    if (int32_t r = check_records(aos, d_force, n)) return r;
 
     char* base = (char*)ws;
     void* state = base;
