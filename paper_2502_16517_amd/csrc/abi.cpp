@@ -771,12 +771,13 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     a.qhead = META_QHEAD_F;
     hipStream_t st = (hipStream_t)stream;
     bool direct = is_direct(v->layout.kind);
-    // windows from the converged h: a member the view only reads is never
-    // modified while it is open, so the records hold it; a view that also
-    // writes h (one view over density and force) holds the density's h
+    // windows from the converged h: from the view when it holds h as a double
+    // (an exact copy, or the density's h in a view over both loops), else from
+    // the records (a member the view only reads is never modified while it is
+    // open; an FP32 view holds it rounded to float)
     const FieldPlan& hp = v->plan[v->role_field[SPHV_H]];
     hipError_t e;
-    if (!direct && (hp.f.access & SPHV_OUT)) {
+    if (!direct && hp.view_dtype == SPHV_F64) {
         const Access va = acc_view(v);
         e = launch_force_reach(c->dev, ref_view(v, hp), 0, &va, a.g, (DevState*)state, st);
     } else {
@@ -797,23 +798,28 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
     for (int k = 0; k < 5; ++k) if (int32_t s = need(v, rout[k], SPHV_OUT)) return s;
     if (int32_t s = records_ok(v)) return s;
     if (v->n == 0) return SPHV_OK;
-    // inputs from the records (A_in members are never modified while the view
-    // is open), outputs from where the loop wrote them; h from the view when
-    // the view also writes it (one view over density and force)
+    // outputs from where the loop wrote them; inputs from the view when it
+    // holds them as doubles (an FP64 view: exact copies, or the density's h
+    // in a view over both loops), else from the records (members a view only
+    // reads are never modified while it is open)
     const bool direct = is_direct(v->layout.kind);
+    bool in_view = !direct;
+    for (int k = 0; k < 6; ++k) in_view = in_view && v->plan[v->role_field[rin[k]]].view_dtype == SPHV_F64;
+    if (!direct && !in_view && (v->plan[v->role_field[SPHV_H]].f.access & SPHV_OUT))
+        return SPHV_E_DESCRIPTOR;    // h written in the view but the other inputs stored as floats
     FieldRef in6[6], out5[5];
-    for (int k = 0; k < 6; ++k) in6[k] = ref_rec(v->aos, v->plan[v->role_field[rin[k]]].f);
+    for (int k = 0; k < 6; ++k) {
+        const FieldPlan& fp = v->plan[v->role_field[rin[k]]];
+        in6[k] = in_view ? ref_view(v, fp) : ref_rec(v->aos, fp.f);
+    }
     for (int k = 0; k < 5; ++k) {
         const FieldPlan& fp = v->plan[v->role_field[rout[k]]];
         out5[k] = direct ? ref_rec(v->aos, fp.f) : ref_view(v, fp);
     }
-    const FieldPlan& hp = v->plan[v->role_field[SPHV_H]];
-    const bool h_in_view = !direct && (hp.f.access & SPHV_OUT);
-    const FieldRef hv = h_in_view ? ref_view(v, hp) : in6[5];
     Access ra = acc_rec(v->index, v->desc.stride);
     Access oa = direct ? ra : acc_view(v);
-    return hip_status(launch_force_reduce(in6, ra, out5, oa, direct, h_in_view ? &hv : nullptr, (DevState*)state,
-                                          p->cfl, v->n, v->red_part, (hipStream_t)stream));
+    return hip_status(launch_force_reduce(in6, ra, out5, oa, direct, in_view, (DevState*)state, p->cfl, v->n,
+                                          v->red_part, (hipStream_t)stream));
 }
 
 // -------------------------------------------------------------- kick/drift

@@ -148,9 +148,9 @@ hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, cons
                           const Access& dst_acc, int64_t n, hipStream_t s);
 hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
 hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
-// hview not null: h is read from there (with outacc) instead of in6[5]
+// in_view: in6 are members of the view (read with outacc) instead of the records
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
-                               const Access& outacc, int out_direct, const FieldRef* hview, DevState* st,
+                               const Access& outacc, int out_direct, int in_view, DevState* st,
                                double cfl, int64_t n, double* partials, hipStream_t s);
 // whole records: dst[didx ? didx[p] : p] = src[sidx ? sidx[p] : p], stride bytes
 // each (stride and both bases multiples of 4 bytes)

@@ -1291,17 +1291,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
 // ============================================ time step and conservation sums
 
 struct RedArgs {
-    FieldRef in[6];     // m vx vy vz u h   (records, through the index)
+    FieldRef in[6];     // m vx vy vz u h   (records through the index, or the view)
     FieldRef out[5];    // ax ay az u_dt v_sig (view or records)
-    FieldRef hview;     // h where the outputs are, when h_in_view
     Access rec;
     Access outacc;
     DevState* state;
     double* part;       // [nblocks][16]
     int64_t n;
     double cfl;
-    int32_t h_in_view;  // h was written into the view by an earlier loop on it
-    int32_t pad;
 };
 
 constexpr int kRedThreads = 256;
@@ -1321,8 +1318,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(RedArgs r)
         const Loc<DIRECT_OUT> lo = locate<DIRECT_OUT>(r.outacc, p);
         const double m = ld_f64(r.in[0], lr);
         const double vx = ld_f64(r.in[1], lr), vy = ld_f64(r.in[2], lr), vz = ld_f64(r.in[3], lr);
-        const double u = ld_f64(r.in[4], lr);
-        const double h = r.h_in_view ? ld_f64(r.hview, lo) : ld_f64(r.in[5], lr);
+        const double u = ld_f64(r.in[4], lr), h = ld_f64(r.in[5], lr);
         const double ax = ld_f64(r.out[0], lo), ay = ld_f64(r.out[1], lo), az = ld_f64(r.out[2], lo);
         const double du = ld_f64(r.out[3], lo), vs = ld_f64(r.out[4], lo);
         s[0] += m * vx;
@@ -1352,7 +1348,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_part(RedArgs r)
 // k_reduce_part with the records' members staged through LDS: the block's
 // kRedBlock particles in rounds of kStageThreads, thread t taking particles
 // base + t, base + t + kStageThreads, ...; then the same tree as above.
-template <bool DIRECT_OUT>
+template <bool DIRECT_OUT, bool IN_VIEW>
 __global__ __launch_bounds__(kStageThreads) void k_reduce_staged(RedArgs r, StagePlan sp)
 {
     extern __shared__ uint4 tile[];
@@ -1364,15 +1360,21 @@ __global__ __launch_bounds__(kStageThreads) void k_reduce_staged(RedArgs r, Stag
     for (int round = 0; round < kRedBlock / kStageThreads; ++round) {
         const int64_t r0 = base + (int64_t)round * kStageThreads;
         if (r0 >= r.n) break;                 // the same for the whole block
-        stage_in(tile, r.in[0].base, r.rec.stride, r.rec.index, r0, r.n, sp);
+        if constexpr (!IN_VIEW) stage_in(tile, r.in[0].base, r.rec.stride, r.rec.index, r0, r.n, sp);
         const int64_t p = r0 + threadIdx.x;
         if (p < r.n) {
-            const LocTile lr{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
             const Loc<DIRECT_OUT> lo = locate<DIRECT_OUT>(r.outacc, p);
-            const double m = ld_f64(r.in[0], lr);
-            const double vx = ld_f64(r.in[1], lr), vy = ld_f64(r.in[2], lr), vz = ld_f64(r.in[3], lr);
-            const double u = ld_f64(r.in[4], lr);
-            const double h = r.h_in_view ? ld_f64(r.hview, lo) : ld_f64(r.in[5], lr);
+            double in6[6];
+            if constexpr (IN_VIEW) {
+                // the inputs are members of the view, in the outputs' slots
+#pragma unroll
+                for (int k = 0; k < 6; ++k) in6[k] = ld_f64(r.in[k], lo);
+            } else {
+                const LocTile lr{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) in6[k] = ld_f64(r.in[k], lr);
+            }
+            const double m = in6[0], vx = in6[1], vy = in6[2], vz = in6[3], u = in6[4], h = in6[5];
             const double ax = ld_f64(r.out[0], lo), ay = ld_f64(r.out[1], lo), az = ld_f64(r.out[2], lo);
             const double du = ld_f64(r.out[3], lo), vs = ld_f64(r.out[4], lo);
             s[0] += m * vx;
@@ -1577,15 +1579,12 @@ hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int
 }
 
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5, const Access& outacc,
-                               int out_direct, const FieldRef* hview, DevState* st, double cfl, int64_t n,
+                               int out_direct, int in_view, DevState* st, double cfl, int64_t n,
                                double* partials, hipStream_t s)
 {
     RedArgs r;
     for (int k = 0; k < 6; ++k) r.in[k] = in6[k];
     for (int k = 0; k < 5; ++k) r.out[k] = out5[k];
-    r.h_in_view = hview ? 1 : 0;
-    r.pad = 0;
-    r.hview = hview ? *hview : in6[5];
     r.rec = rec;
     r.outacc = outacc;
     r.state = st;
@@ -1594,13 +1593,18 @@ hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const Fie
     r.cfl = cfl;
     int64_t nb = (n + kRedBlock - 1) / kRedBlock;
     if (nb < 1) nb = 1;
-    StagePlan sp;
-    if (n > 0 && plan_stage(r.in, 6, 0u, r.rec.stride, &sp)) {
+    StagePlan sp{};
+    if (in_view && !out_direct) {
+        // inputs and outputs in the view: the staged kernel's order, nothing staged
+        hipLaunchKernelGGL((k_reduce_staged<false, true>), dim3((unsigned)nb), dim3(kStageThreads), 0, s, r, sp);
+    } else if (n > 0 && plan_stage(r.in, 6, 0u, r.rec.stride, &sp)) {
         const size_t lds = kStageThreads * sp.nch * 16;
         if (out_direct)
-            hipLaunchKernelGGL(k_reduce_staged<true>, dim3((unsigned)nb), dim3(kStageThreads), lds, s, r, sp);
+            hipLaunchKernelGGL((k_reduce_staged<true, false>), dim3((unsigned)nb), dim3(kStageThreads), lds, s, r,
+                               sp);
         else
-            hipLaunchKernelGGL(k_reduce_staged<false>, dim3((unsigned)nb), dim3(kStageThreads), lds, s, r, sp);
+            hipLaunchKernelGGL((k_reduce_staged<false, false>), dim3((unsigned)nb), dim3(kStageThreads), lds, s, r,
+                               sp);
     } else if (out_direct) {
         hipLaunchKernelGGL(k_reduce_part<true>, dim3((unsigned)nb), dim3(kRedThreads), 0, s, r);
     } else {
