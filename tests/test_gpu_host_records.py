@@ -25,8 +25,11 @@ def _records(w, where):
     return raw.clone()                    # pageable
 
 
-def _steps(w, where, lay, merged=False, steps=2):
-    st = sv.Stepper(None, sv.params_for(w), layout_density=lay, layout_force=lay, aos=_records(w, where),
+def _steps(w, where, lay, merged=False, steps=2, precision=sv.PREC_FP64):
+    p = sv.params_for(w)
+    if precision == sv.PREC_FP32:
+        p.h_tol = 1e-6
+    st = sv.Stepper(None, p, precision, layout_density=lay, layout_force=lay, aos=_records(w, where),
                     merged=merged)
     for _ in range(steps):
         st.step()
@@ -49,6 +52,18 @@ def test_pinned_host_records_give_device_bits(name, lay, merged):
     assert sa.flags == sb.flags
     assert np.array_equal(bits(a), bits(b))
     assert sa.dt == sb.dt and tuple(sa.sums) == tuple(sb.sums) and sa.pairs_total == sb.pairs_total
+
+
+def test_pinned_host_records_fp32():
+    """The FP32 form reads h and the reduction's inputs from the records (its
+    views hold them as floats): over pinned records, the device bits."""
+    w = inputs.two_state_tube(16, 34)
+    lay = sv.layout(sv.LAYOUT_SOA)
+    a, sa = _steps(w, "device", lay, precision=sv.PREC_FP32)
+    b, sb = _steps(w, "pinned", lay, precision=sv.PREC_FP32)
+    assert sa.flags == sb.flags
+    assert np.array_equal(bits(a), bits(b))
+    assert sa.dt == sb.dt and tuple(sa.sums) == tuple(sb.sums)
 
 
 def test_pinned_host_records_sorted_and_tuned():
