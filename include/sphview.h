@@ -38,7 +38,8 @@
  *    about to enqueue work on records checks their first and last bytes with
  *    hipPointerGetAttributes and fails with SPHV_E_INVALID_ARG, before
  *    enqueuing anything, on memory the device cannot address (pageable
- *    host memory); a view is checked at its first gather or loop call.
+ *    host memory, another device's memory); a view is checked at its first
+ *    gather or loop call.
  *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work is enqueued asynchronously on it; only sphv_read_state and
  *    sphv_write_state synchronise with the host.

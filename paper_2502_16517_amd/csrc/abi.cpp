@@ -894,9 +894,10 @@ void sphv_graph_destroy(sphv_graph* g)
 
 namespace sphv {
 namespace {
-// An address the kernels may dereference: device or managed memory, or pinned
-// host memory that the device maps at the same address (hipHostMalloc).
-// Pageable host memory is not mapped: a kernel reading it would fault.
+// An address the kernels may dereference: memory of the current device,
+// managed memory, or pinned host memory that the device maps at the same
+// address (hipHostMalloc).  Pageable host memory is not mapped, and another
+// device's memory needs peer access: a kernel reading either could fault.
 bool device_addressable(const void* p)
 {
     hipPointerAttribute_t a;
@@ -904,7 +905,11 @@ bool device_addressable(const void* p)
         (void)hipGetLastError();
         return false;
     }
-    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return true;
+    if (a.type == hipMemoryTypeManaged) return true;
+    if (a.type == hipMemoryTypeDevice) {
+        int dev = -1;
+        return hipGetDevice(&dev) == hipSuccess && a.device == dev;
+    }
     return a.type == hipMemoryTypeHost && a.devicePointer == p;
 }
 }  // namespace
