@@ -350,9 +350,12 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p,
  * fixed-order FP64 tree (deterministic), dt = cfl min_i h_i / v_sig,i (the
  * division rounded per particle) and the conservation sums of sphv_state.
  * Updates the state block: t += old dt, dt_prev = old dt, dt = new dt,
- * nstep += 1.  Inputs m, v, u, h are read from the records (members a view
- * only reads are never modified while it is open), outputs from the view; h
- * from the view when the view writes it (one view over both loops). */
+ * nstep += 1.  Outputs are read from where the loop wrote them.  Inputs m,
+ * v, u, h are read from an FP64 view, which holds them as exact copies (or
+ * holds the density's h, in one view over both loops).  Otherwise they come
+ * from the records: members a view only reads are never modified while it
+ * is open, and an FP32 view holds them as floats.  The sums do not depend on
+ * the source.  The force loop's windows take h from the same place. */
 int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state_dev, void* stream);
 
 /* Kick / drift / kick with prediction (paper Sec. 2.1 steps 3-5) on the records
