@@ -126,3 +126,23 @@ def test_quartic_full_tube_sampled_parity(orc):
     wf = check_force(out, oracle_force(orc, w, dens, targets=idx, kernel=Q), idx=idx, tol=1e-12,
                      vsig_tol=1e-14)
     print("quartic tube64 density", wd, "force", wf, flush=True)
+
+
+def test_quartic_full_kh128_sampled_parity(orc):
+    """The 128^3 Kelvin-Helmholtz shear layer (2,097,152 particles) with the
+    quartic kernel: every output of 400 sampled particles against the oracle."""
+    w = inputs.config3()
+    st = sv.Stepper(w.rec, sv.params_for(w, kernel=Q))
+    st.build()
+    st.density()
+    dens = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    assert state.flags & ~sv.F_OUT_OF_BOX == 0, state.flags
+    idx = np.sort(np.random.default_rng(4).choice(w.n, size=400, replace=False))
+    wd = check_density(dens, oracle_density(orc, w, targets=idx, kernel=Q), idx=idx, tol=1e-12)
+    wf = check_force(out, oracle_force(orc, w, dens, targets=idx, kernel=Q), idx=idx, tol=1e-12,
+                     vsig_tol=1e-14)
+    print("quartic kh128 density", wd, "force", wf, flush=True)
