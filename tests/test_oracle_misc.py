@@ -63,6 +63,55 @@ def test_relative_f32_rounding(orc):
     assert np.all(np.abs(rel) <= 1 / 48 + 1e-7)
 
 
+def test_relative_f32_hand_derived_3d(orc):
+    """Cell-relative FP32 coordinates (Sec. 4.2, the AoS-to-SoA operator with a
+    change of representation) worked by hand on a 4 x 5 x 6 grid over the box
+    [-1, 1] x [0, 1] x [2, 5]: cells 0.5 x 0.2 x 0.5.
+      (0.3, 0.65, 3.7):   k = (2, 3, 3), key = (3*5 + 3)*4 + 2 = 74,
+                          corner (0, 0.6, 3.5), offsets (0.3, 0.05, 0.2);
+      (-0.9, 0.99, 4.99): k = (0, 4, 5), key = (5*5 + 4)*4 + 0 = 116,
+                          corner (-1, 0.8, 4.5), offsets (0.1, 0.19, 0.49).
+    Every axis has a non-zero cell index in the first point, so a swapped key
+    decoding or a cell-centre origin moves some offset by at least 0.1."""
+    grid, lo, L = (4, 5, 6), (-1.0, 0.0, 2.0), (2.0, 1.0, 3.0)
+    cell = tuple(l / g for l, g in zip(L, grid))
+    inv = tuple(g / l for g, l in zip(grid, L))
+    pts = np.array([[0.3, 0.65, 3.7], [-0.9, 0.99, 4.99]])
+    keys = orc.bin_keys(pts[:, 0], pts[:, 1], pts[:, 2], lo, inv, grid)
+    assert keys.tolist() == [74, 116]
+    expect = np.array([[0.3, 0.05, 0.2], [0.1, 0.19, 0.49]])
+    for axis in range(3):
+        rel = orc.relative_f32(pts[:, axis], keys, grid, lo, cell, axis)
+        assert rel.dtype == np.float32
+        # the real offset, to within one float32 ulp plus the rounding of the inputs
+        tol = np.spacing(expect[:, axis].astype(np.float32)).astype(np.float64) + 1e-15
+        assert np.all(np.abs(rel.astype(np.float64) - expect[:, axis]) <= tol), (axis, rel)
+
+
+@pytest.mark.parametrize("gen", ["config1", "tube", "config3"])
+def test_relative_f32_inside_own_cell(orc, gen):
+    """Every particle of the lattice, the two-state tube and the 128^3 shear
+    layer: its offset from the corner of the cell bin_keys puts it in lies in
+    [0, c) along each axis (the face rule: a coordinate whose scaled offset
+    rounds onto the next face may sit a few ulp below it), both before and
+    after the rounding to float."""
+    w = {"config1": inputs.config1, "tube": lambda: inputs.two_state_tube(16, 7),
+         "config3": inputs.config3}[gen]()
+    S = inputs.SLOT
+    cell = tuple(l / g for l, g in zip(w.length, w.grid))
+    inv = tuple(g / l for g, l in zip(w.grid, w.length))
+    pos = [w.rec[:, S[k]] for k in ("x", "y", "z")]
+    keys = orc.bin_keys(*pos, w.lo, inv, w.grid)
+    for axis in range(3):
+        rel = orc.relative_f32(pos[axis], keys, w.grid, w.lo, cell, axis).astype(np.float64)
+        c = cell[axis]
+        slack = 8 * np.spacing(np.float64(w.lo[axis] + w.length[axis]))
+        assert rel.min() >= -slack, (axis, rel.min())
+        assert rel.max() <= np.float64(np.float32(c)), (axis, rel.max(), c)
+        # occupancy of the whole cell span: offsets reach close to both faces
+        assert rel.max() > 0.5 * c
+
+
 # ------------------------------------------------------------ binning, sort
 
 def test_binning_against_brute_force(orc):
@@ -154,6 +203,16 @@ def test_kick_drift_wraps_periodic(orc):
     assert 0.0 <= r[0, S["x"]] < 1.0 and 0.0 <= r[1, S["x"]] < 1.0
     assert math.isclose(r[0, S["x"]], 0.009, abs_tol=1e-15)
     assert math.isclose(r[1, S["x"]], 0.991, abs_tol=1e-15)
+
+
+def test_time_step_takes_the_smallest_ratio(orc):
+    """dt = C min_i h_i / v_sig,i with unequal h and v_sig: the ratios are 0.1
+    and 0.05, so dt = 0.3 * 0.05 = 0.015; the largest ratio would give 0.03,
+    min h / max v_sig 0.025 and min h / min v_sig 0.03."""
+    h = np.array([0.1, 0.2])
+    vsig = np.array([1.0, 4.0])
+    assert math.isclose(orc.time_step(h, vsig, 0.3), 0.015, rel_tol=1e-15)
+    assert math.isclose(orc.time_step(h[::-1], vsig[::-1], 0.3), 0.015, rel_tol=1e-15)
 
 
 def test_conservation_sums(orc):
