@@ -80,7 +80,11 @@ enum {
     SPHV_F_QUEUE_OVERFLOW = 1u << 3,   /* work items exceeded the planned capacity      */
     SPHV_F_NONFINITE_OUTPUT = 1u << 4, /* NaN/inf density or force result               */
     SPHV_F_GRID_TOO_SMALL = 1u << 5,   /* a reach window wraps onto itself (periodic)   */
-    SPHV_F_OUT_OF_BOX = 1u << 6        /* a particle lies outside an open box           */
+    SPHV_F_OUT_OF_BOX = 1u << 6        /* a particle lies outside an open box, or       */
+                                       /* outside [lo, lo+len) on a periodic axis: the  */
+                                       /* records must hold wrapped coordinates (such a */
+                                       /* particle is binned into an edge cell, and     */
+                                       /* pairs across that face may be missed)         */
 };
 
 const char* sphv_status_string(int32_t status);
@@ -306,7 +310,9 @@ int32_t sphv_view_create(sphv_view** out, const sphv_descriptor* d, int64_t n,
  * (Sec. 3.1).  cells is required for FP32 views (cell of each element) and may
  * be NULL otherwise.  Fails with SPHV_E_ALIAS if another open view on
  * overlapping records writes a member this one touches, or touches a member
- * this one writes. */
+ * this one writes; views of kind SPHV_LAYOUT_DIRECT and SPHV_LAYOUT_SORTED
+ * (which copy nothing but write the records' members in place) open and
+ * take part in this rule like the others. */
 int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream);
 /* Scatter A_out only (the epilogue) and close the view. */
 int32_t sphv_soa_to_aos(sphv_view* v, void* stream);
@@ -362,7 +368,9 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state_dev, vo
  * directly (linear loop, no view), every product and sum rounded on its own:
  *   if nstep > 1: v = vh + a (dt_prev/2), u = uh + u_dt (dt_prev/2)   (close step)
  *   vh = v + a (dt/2), uh = u + u_dt (dt/2)                           (open step)
- *   x = x + vh dt, wrapped once into [lo, lo+len) on periodic axes     (drift)
+ *   x = x + vh dt, wrapped once into [lo, lo+len) on periodic axes     (drift;
+ *       a drift over more than one box length stays outside and the next
+ *       sphv_cells_build sets SPHV_F_OUT_OF_BOX)
  *   v = vh + a (dt/2), u = uh + u_dt (dt/2)                           (predict)
  * dt, dt_prev and nstep are read from the device state block.  Members: x, y, z,
  * vx, vy, vz, vhx, vhy, vhz, ax, ay, az, u, uh, u_dt. */

@@ -613,7 +613,9 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     // gather (a view on the records is checked by the first loop call instead)
     if (!is_direct(v->layout.kind))
         if (int32_t r = records_ok(v)) return r;
-    if (!is_direct(v->layout.kind)) {
+    {
+        // views on the records themselves (direct, sorted) write the records'
+        // members in place, so they take part in the rule like any other view
         std::lock_guard<std::mutex> lk(g_open_mutex);
         for (sphv_view* o : g_open)
             if (views_conflict(v, o)) return SPHV_E_ALIAS;

@@ -94,9 +94,15 @@ __device__ __forceinline__ void bin_one(const double c[3], double h, const Geom&
     }
     hbits = __float_as_uint(H);
     if (!finite) set_flag(st, SPHV_F_NONFINITE_INPUT);
-    bool open_out = false;
-    for (int d = 0; d < 3; ++d) open_out |= (!g.periodic[d] && outside);
-    if (finite && open_out) set_flag(st, SPHV_F_OUT_OF_BOX);
+    // open axes: outside the grid; periodic axes: outside [lo, lo + len), the
+    // range kick_drift wraps into (an unwrapped coordinate is binned into an
+    // edge cell whose window would miss some of its pairs)
+    bool out_of_box = false;
+    for (int d = 0; d < 3; ++d) {
+        if (g.periodic[d]) out_of_box |= !(c[d] >= g.lo[d] && c[d] < __dadd_rn(g.lo[d], g.len[d]));
+        else out_of_box |= outside;
+    }
+    if (finite && out_of_box) set_flag(st, SPHV_F_OUT_OF_BOX);
 }
 
 __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,

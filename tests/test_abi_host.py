@@ -169,6 +169,32 @@ def test_alias_rule_between_open_views():
         sv.view_destroy(v)
 
 
+@pytest.mark.parametrize("kinds", [(sv.LAYOUT_DIRECT, sv.LAYOUT_SOA), (sv.LAYOUT_SOA, sv.LAYOUT_DIRECT),
+                                   (sv.LAYOUT_SORTED, sv.LAYOUT_AOSOA)])
+def test_alias_rule_covers_views_on_the_records(kinds):
+    """A view that loops on the records themselves writes their members in
+    place: it may not open beside a view that holds copies of what it writes,
+    nor the other way round (paper Sec. 3.3)."""
+    fake = 1 << 40
+    dd, df = sv.density_descriptor(), sv.force_descriptor()
+    la = sv.layout(kinds[0], 8 if kinds[0] == sv.LAYOUT_AOSOA else 0)
+    lb = sv.layout(kinds[1], 8 if kinds[1] == sv.LAYOUT_AOSOA else 0)
+    va = sv.view_create(dd, 0, la, sv.PREC_FP64, fake, None, fake, 1 << 20)
+    vb = sv.view_create(df, 0, lb, sv.PREC_FP64, fake, None, fake + (1 << 20), 1 << 20)
+    sv.aos_to_soa(va)
+    with pytest.raises(sv.SphvError) as e:
+        sv.aos_to_soa(vb)                 # force reads h, rho, omega that density writes
+    assert e.value.status == sv.E_ALIAS
+    sv.soa_to_aos(va)
+    sv.aos_to_soa(vb)
+    with pytest.raises(sv.SphvError) as e:
+        sv.aos_to_soa(va)                 # and the other way round
+    assert e.value.status == sv.E_ALIAS
+    sv.soa_to_aos(vb)
+    for v in (va, vb):
+        sv.view_destroy(v)
+
+
 def test_disjoint_views_do_not_conflict():
     fake = 1 << 40
     l = sv.layout()

@@ -226,3 +226,27 @@ def _run_density_records(w, rec=None):
     out, state = run_density(w, rec=rec)
     assert state.flags == 0
     return out
+
+
+@pytest.mark.parametrize("where", ["above", "below", "inside"])
+def test_unwrapped_periodic_coordinate_is_flagged(orc, where):
+    """A coordinate outside [lo, lo + len) on a periodic axis sets
+    SPHV_F_OUT_OF_BOX (it is binned into an edge cell, whose window misses
+    pairs across that face); wrapped records set no flag."""
+    print(f"[cells] periodic face {where}", flush=True)
+    w = inputs.config1()
+    rec = w.rec.copy()
+    if where == "above":
+        rec[7, S["y"]] = np.nextafter(1.0, 2.0)          # just past the upper face
+    elif where == "below":
+        rec[7, S["z"]] = -1e-9                            # just below the lower face
+    else:
+        rec[7, S["x"]] = np.nextafter(1.0, 0.0)          # the last double inside
+    st = sv.Stepper(rec, sv.params_for(w))
+    st.build()
+    state = st.read_state()
+    st.close()
+    if where == "inside":
+        assert state.flags == 0
+    else:
+        assert state.flags & sv.F_OUT_OF_BOX
