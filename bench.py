@@ -3,18 +3,21 @@
 One step = cells_build, the density view (gather, density with the
 smoothing-length iteration, scatter), the force view (gather, force, time-step
 and conservation reduction, scatter) and kick_drift, all through the C-ABI on
-one stream.  The workload (--workload, default tube64) is the two-state tube: a 64^3 lattice (density 1,
-pressure 1) beside a 32^3 lattice (density 1/8, pressure 0.1) in the periodic
-box [0,2]x[0,1]^2, 294,912 particles in 256-byte records, FP64.
+one stream.  The workload (--workload, default kh256) is the largest
+single-GPU configuration: the Kelvin-Helmholtz shear layer on a 256^3 lattice
+(16,777,216 particles) in the periodic unit box, 256-byte records, FP64.
 
 Before the timed runs the library's tuner picks, untimed, each loop's layout
 and tile shape on the same records (with --tune-grid also the grid: cells per
 support length 1, 2 or 3); the timed steps run with that choice (--no-tune:
-SoA views).  The grid is otherwise the generated one, two cells per support of
-the right state's h.
+SoA views).  The grid is otherwise the generated one (one cell spans the
+support 2h with 10 % headroom).
 
 value = (density pairs + force pairs) per second over the timed steps, the pairs
 counted by the kernels themselves (j != i inside the support at the accepted h).
+Besides the FP64 form the line carries the FP32 form on the same workload and
+the batched form (FP32 pairs, graph-replayed steps) on the 2^20-particle
+Plummer sphere, each with its speedup over the plain FP64 GPU form there.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -31,12 +34,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# algorithmic flops per true pair (FMA = 2, sqrt and division = 1 each), counted
-# on the pair formulas of the density and force loops, per smoothing kernel: the
-# quartic's w and w' take 11 more than the cubic's, its w' alone 7 more (twice
-# per force pair)
-FLOPS_DENSITY_PAIR = {"cubic": 26, "quartic": 37}
-FLOPS_FORCE_PAIR = {"cubic": 67, "quartic": 81}
+# algorithmic flops per true pair (FMA = 2, sqrt and division = 1 each) of the
+# density and the force formulas, per smoothing kernel: 31 and 75 for the cubic
+# spline; the quartic's w and w' take 11 more per density pair, its w' 7 more
+# per side of a force pair
+FLOPS_DENSITY_PAIR = {"cubic": 31, "quartic": 42}
+FLOPS_FORCE_PAIR = {"cubic": 75, "quartic": 89}
+# algorithmic bytes per particle of each piece of the FP64 converted step:
+# members read + members written (a density pass reads x, y, z, m, h and
+# writes h, rho, omega, wcount; the force loop reads 12 members and writes 5)
+BYTES_FP64 = {"density_gather": 40 + 40, "density_loop_pass": 40 + 32, "density_scatter": 32 + 32,
+              "force_gather": 96 + 96, "force_loop": 96 + 40, "reduce": 48 + 40, "force_scatter": 40 + 40,
+              "kick_drift": 120 + 88}
 PEAK_FP64_VALU = 256 * 2.4e9 * 128          # 256 CUs x 2.4 GHz x 64 FMA lanes: 78.6 TFLOP/s
 PEAK_FP32_VALU = 157.3e12                   # published, needs packed FP32
 HBM_PEAK = 8.0e12
@@ -46,8 +55,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_loops_tube64_fp64_counters.md")
 PAIR_SRC = os.path.join(ROOT, "paper_2502_16517_amd", "csrc", "k_pair.hip")
+TRAFFIC_FILE = None     # the committed counter summary of the workload (set in main)
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"pair_loops_{workload}_fp64_counters.md")
 
 
 def profiled_choice():
@@ -56,7 +69,7 @@ def profiled_choice():
     try:
         text = open(TRAFFIC_FILE).read()
         src = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()[:16]
-    except OSError:
+    except (OSError, TypeError):
         return None
     for line in text.splitlines():
         line = line.strip()
@@ -83,7 +96,7 @@ def measured_traffic(choice):
     try:
         text = open(TRAFFIC_FILE).read()
         src = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()[:16]
-    except OSError:
+    except (OSError, TypeError):
         return {}
     for line in text.splitlines():
         line = line.strip()
@@ -194,7 +207,7 @@ def choice_of(sv, tuned):
             "force_layout": sv.layout_name(lf)}
 
 
-EVENTS = ("built", "d_gathered", "d_loop", "d_scattered", "f_gathered", "f_loop", "reduced", "f_scattered",
+EVENTS = ("start", "built", "d_gathered", "d_loop", "d_scattered", "f_gathered", "f_loop", "reduced", "f_scattered",
           "kicked")
 
 
@@ -222,6 +235,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
             sv.graph_launch(g, s)
             continue
         e = ev[k]
+        e["start"].record(s)
         sv.begin_step(st.state, s)
         sv.cells_build(st.cells, st.aos, st.d_cells, st.state, s)
         e["built"].record(s)
@@ -257,7 +271,7 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
         res["ms_force"] = span("f_gathered", "f_loop")
         # the span of the two views: first density gather to last force scatter
         res["ms_span"] = span("built", "f_scattered")
-        for name, a, b in (("density_gather", "built", "d_gathered"), ("density_scatter", "d_loop", "d_scattered"),
+        for name, a, b in (("cells", "start", "built"), ("density_gather", "built", "d_gathered"), ("density_scatter", "d_loop", "d_scattered"),
                            ("force_gather", "d_scattered", "f_gathered"), ("force_scatter", "reduced", "f_scattered"),
                            ("kick_drift", "f_scattered", "kicked"), ("reduce", "f_loop", "reduced")):
             res["ms_" + name] = span(a, b)
@@ -295,43 +309,77 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return {"GB/s": rate / 1e9, "frac_of_peak": rate / HBM_PEAK, "bytes": 2 * (mib << 20), "ms": best}
 
 
-def cpu_baseline(inputs, w, kernel=0, reps=3):
-    """The oracle (plain scalar C, OpenMP over its target particles, all host
-    threads) on one step of the same workload: density with the h iteration
-    for every particle, then the force for every particle from the oracle's own
-    density, `reps` times (about 15 thread-seconds of CPU work on 16 cores)."""
+def cpu_model():
+    name = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return name
+
+
+def cpu_baseline(inputs, w, kernel=0, sample_single=200_000, sample_all=1_000_000, seed=16517):
+    """The oracle (plain scalar C; OpenMP over its target particles) timed on
+    the host cores, on a bounded sample of one step of the same workload,
+    single-threaded and on every host thread.
+
+    The sample is a contiguous run of target particles in record order (as
+    one thread of a whole step walks them), starting at a seeded offset.  Per
+    thread count: density with the smoothing-length iteration, then the force,
+    at those targets; each call also builds the oracle's cell list over all N
+    particles, a fixed cost timed on its own with a single target.  The step
+    estimate is that fixed cost plus the per-target cost times N, and its pairs
+    the sample's mean pairs per target times N.  The force reads, for every
+    particle, h as recorded, rho = m eta^3 / h^3 (the state the iteration
+    converges to) and omega = 1, so it does not depend on a density pass over
+    all N."""
     import numpy as np
 
     from oracle import oracle as orc
 
     S = inputs.SLOT
     rec = w.rec
+    n = w.n
     box = orc.box_of(w.lo, w.length, w.periodic)
     c = {k: np.ascontiguousarray(rec[:, S[k]]) for k in S if k not in inputs.INT_SLOTS}
-    nthreads = orc.max_threads()
-    td = tf = 0.0
-    for _ in range(reps):
+    rho = c["m"] * w.eta ** 3 / c["h"] ** 3
+    omega = np.ones(n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def run(targets, nthreads):
         t0 = time.perf_counter()
-        d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads, kernel=kernel)
+        d = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, nthreads=nthreads, kernel=kernel,
+                        targets=targets)
         t1 = time.perf_counter()
-        f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], d["h"], d["rho"], d["omega"],
-                      c["u"], c["alpha"], box, inputs.GAMMA, nthreads=nthreads, kernel=kernel)
+        f = orc.force(c["x"], c["y"], c["z"], c["vx"], c["vy"], c["vz"], c["m"], c["h"], rho, omega, c["u"],
+                      c["alpha"], box, inputs.GAMMA, nthreads=nthreads, kernel=kernel, targets=targets)
         t2 = time.perf_counter()
-        td += t1 - t0
-        tf += t2 - t1
-    pairs = int(d["count"].sum()) + int(f["count"].sum())
-    cpu = platform.processor() or platform.machine()
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": reps * pairs / (td + tf), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{reps} full steps of the same {w.n}-particle workload (per step: density with h "
-                      f"iteration {td / reps:.2f} s + force {tf / reps:.2f} s wall, {nthreads} threads, {cpu})",
-            "pairs": pairs}
+        return t1 - t0, t2 - t1, int(d["count"].sum()) + int(f["count"].sum())
+
+    out = {}
+    for label, nthreads, size in (("single", 1, sample_single), ("all", orc.max_threads(), sample_all)):
+        size = min(size, n)
+        i0 = int(rng.integers(0, n - size + 1))
+        targets = np.arange(i0, i0 + size, dtype=np.int64)
+        fd, ff, _ = run(targets[:1], nthreads)
+        td, tf, pairs = run(targets, nthreads)
+        fixed = fd + ff
+        per_target = max(td + tf - fixed, 1e-12) / size
+        t_step = fixed + per_target * n
+        pairs_step = pairs * n / size
+        out[label] = {"value": pairs_step / t_step, "threads": nthreads, "targets": size, "first_target": i0,
+                      "s_sample": td + tf, "s_fixed": fixed, "s_step_estimate": t_step,
+                      "pairs_step_estimate": pairs_step}
+    a = out["all"]
+    return {"value": a["value"], "unit": "pairs/s", "cores": a["threads"], "kind": "oracle",
+            "sample": (f"{a['targets']} and {out['single']['targets']} consecutive target particles of the "
+                       f"{n}-particle workload (density with h iteration + force, pairs = density + force "
+                       f"pairs), on {a['threads']} and 1 threads, extrapolated to one step: "
+                       f"{a['s_step_estimate']:.1f} s and {out['single']['s_step_estimate']:.1f} s per step"),
+            "single_thread": out["single"]["value"], "all_threads": out["all"],
+            "single": out["single"], "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def host_records(torch, sv, inputs, w, desc, args):
@@ -382,8 +430,9 @@ def main():
                     help="skip the extra timing of one view over both loops (the tuned layouts that are views)")
     ap.add_argument("--no-other-kernel", action="store_true",
                     help="skip the extra timing of the other smoothing kernel with the same layouts")
-    ap.add_argument("--workload", default="tube64", choices=list(WORKLOADS),
-                    help="tube64 is the headline; the others are the parity workloads, for context")
+    ap.add_argument("--workload", default="kh256", choices=list(WORKLOADS),
+                    help="kh256 (the largest configuration) is the headline; the others are the parity "
+                         "workloads, for context")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the tuner: SoA views for both loops")
     ap.add_argument("--layouts", default=None,
@@ -392,6 +441,9 @@ def main():
     ap.add_argument("--tune-grid", action="store_true",
                     help="let the tuner pick the grid too (it times one snapshot of the particles; over the "
                          "timed steps the generated grid did better on this workload)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched form (FP32 pairs, graph replay) on the Plummer sphere")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic kernel for "
                          "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -423,6 +475,8 @@ def main():
     if not args.calib_copy_mib:
         hbm_copy = copy_bandwidth(torch)
         log(f"[bench] device copy: {hbm_copy['GB/s']:.0f} GB/s (read + write)")
+    global TRAFFIC_FILE
+    TRAFFIC_FILE = traffic_file(args.workload)
     gen, pkw, desc = WORKLOADS[args.workload]
     PKW.update(pkw)
     PKW["kernel"] = KERNELS[args.kernel]
@@ -505,6 +559,8 @@ def main():
 
     ms_step = r64["ms_total"] / args.steps
     value = r64["pairs"] / (r64["ms_total"] / 1e3)
+    n = w.n
+    passes = evals_d / max(pairs_d, 1)          # density passes per particle, on average
     # dominant kernel: the larger of the two pair loops
     dens_flops = evals_d * FLOPS_DENSITY_PAIR[args.kernel]
     force_flops = pairs_f * FLOPS_FORCE_PAIR[args.kernel]
@@ -522,27 +578,54 @@ def main():
                 "traffic": traffic,
                 # the counters' run used the same kernel; its layout, when another
                 "traffic_layout": traffic_layout,
-                "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12},
-                "force": {"ms": r64["ms_force"], "tflops": force_flops / (r64["ms_force"] / 1e3) / 1e12}}
+                "flops_per_pair": {"density": FLOPS_DENSITY_PAIR[args.kernel],
+                                   "force": FLOPS_FORCE_PAIR[args.kernel]},
+                "density": {"ms": r64["ms_density"], "tflops": dens_flops / (r64["ms_density"] / 1e3) / 1e12,
+                            "pair_evals": evals_d},
+                "force": {"ms": r64["ms_force"], "tflops": force_flops / (r64["ms_force"] / 1e3) / 1e12,
+                          "pairs": pairs_f}}
 
     # conversions (the paper's prologue and epilogue) and kick_drift: algorithmic
     # bytes (members read + members written, per particle) over their event times
-    n = w.n
-    fp64_view = {"density_gather": 40 + 40, "density_scatter": 32 + 32, "force_gather": 96 + 96,
-                 "force_scatter": 40 + 40, "kick_drift": 120 + 88}
     conv = {}
-    for name, per in fp64_view.items():
+    for name in ("density_gather", "density_scatter", "force_gather", "force_scatter", "kick_drift"):
         direct = (name.startswith("density") and t64[1].kind in (sv.LAYOUT_DIRECT, sv.LAYOUT_SORTED)) or \
                  (name.startswith("force") and t64[2].kind in (sv.LAYOUT_DIRECT, sv.LAYOUT_SORTED))
         ms = r64["ms_" + name]
+        per = BYTES_FP64[name]
         conv[name] = {"ms": ms, "bytes": 0 if direct and name != "kick_drift" else per * n,
                       "GB/s": None if direct and name != "kick_drift" else per * n / (ms / 1e3) / 1e9}
         if conv[name]["GB/s"] is not None:
             conv[name]["hbm_frac"] = conv[name]["GB/s"] * 1e9 / HBM_PEAK
 
+    # lower bound of each piece of the span: max(algorithmic bytes / HBM peak,
+    # algorithmic flops / FP64 vector peak); the fraction reported is
+    # T_lower / T_measured, per piece and for the span (conversions, both
+    # loops with every density pass, the step reduction)
+    def t_lower(nbytes, nflops=0.0):
+        return max(nbytes / HBM_PEAK, nflops / PEAK_FP64_VALU) * 1e3
+    pieces = {
+        "density_gather": (t_lower(n * BYTES_FP64["density_gather"]), r64["ms_density_gather"]),
+        "density_loop": (t_lower(n * BYTES_FP64["density_loop_pass"] * passes, dens_flops), r64["ms_density"]),
+        "density_scatter": (t_lower(n * BYTES_FP64["density_scatter"]), r64["ms_density_scatter"]),
+        "force_gather": (t_lower(n * BYTES_FP64["force_gather"]), r64["ms_force_gather"]),
+        "force_loop": (t_lower(n * BYTES_FP64["force_loop"], force_flops), r64["ms_force"]),
+        "reduce": (t_lower(n * BYTES_FP64["reduce"]), r64["ms_reduce"]),
+        "force_scatter": (t_lower(n * BYTES_FP64["force_scatter"]), r64["ms_force_scatter"]),
+    }
+    d4 = {k: {"t_lower_ms": lo, "t_ms": t, "frac": lo / t if t > 0 else None} for k, (lo, t) in pieces.items()}
+    span_lower = sum(lo for lo, _ in pieces.values())
+    d4["span"] = {"t_lower_ms": span_lower, "t_ms": r64["ms_span"], "frac": span_lower / r64["ms_span"]}
+    d4["kick_drift"] = {"t_lower_ms": t_lower(n * BYTES_FP64["kick_drift"]), "t_ms": r64["ms_kick_drift"],
+                        "frac": t_lower(n * BYTES_FP64["kick_drift"]) / r64["ms_kick_drift"]}
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_form(torch, sv, inputs, args)
+
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "tube64":
-        log("[bench] cpu baseline (oracle)")
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle, sampled)")
         cpu = cpu_baseline(inputs, w, KERNELS[args.kernel])
 
     out = {
@@ -559,30 +642,68 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc + ", 256-byte 32-slot records, FP64",
+                   "name": args.workload,
                    "n": w.n, "grid": list(t64[0]), "tuned": not (args.no_tune or args.layouts),
                    "kernel": args.kernel,
                    "layout": {"density": choice["density_layout"], "force": choice["force_layout"]},
                    "pairs_per_step": {"density": pairs_d, "density_all_passes": evals_d, "force": pairs_f}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "t_lower_over_t": d4,
         "graph": {"value": g64["pairs"] / (g64["ms_total"] / 1e3), "ms_per_step": g64["ms_total"] / args.steps},
         # pairs/s over the two views alone (gathers, loops, reduction, scatters),
         # without cells_build and kick_drift
         "span": {"value": r64["pairs"] / args.steps / (r64["ms_span"] / 1e3), "ms": r64["ms_span"]},
         "fp32": f32,
+        "batched": batched,
         "other_kernel": other,
         # one view over both loops (gather before density, scatter after the reduction)
         "merged_view": merged,
         "conversions": conv,
         "reduce_ms": r64["ms_reduce"],
+        "cells_build_ms": r64["ms_cells"],
         "hbm_frac_step": None,
         "hbm_copy": hbm_copy,
     }
     # whole-step HBM fraction: algorithmic view bytes (gathers, scatters, loop
     # inputs and outputs) over the step time
-    algo_bytes = n * (80 + 64 + 192 + 80) + n * (40 + 32) * max(1, round(evals_d / max(pairs_d, 1))) + n * (96 + 40)
+    algo_bytes = n * (BYTES_FP64["density_gather"] + BYTES_FP64["density_scatter"] + BYTES_FP64["force_gather"] +
+                      BYTES_FP64["force_scatter"] + BYTES_FP64["density_loop_pass"] * passes +
+                      BYTES_FP64["force_loop"])
     out["hbm_frac_step"] = algo_bytes / (ms_step / 1e3) / HBM_PEAK
+    out["hbm_frac_span"] = algo_bytes / (r64["ms_span"] / 1e3) / HBM_PEAK
     print(json.dumps(out), flush=True)
+
+
+def batched_form(torch, sv, inputs, args):
+    """The batching form on the 2^20-particle Plummer sphere (cells of 1 to
+    ~2000 particles): FP32 pairs, the whole step replayed as one HIP graph,
+    against the plain FP64 GPU form (eager) on the same records.  SoA views
+    with the automatic tile shape (no tuning: a trial there costs a step)."""
+    gen, pkw, desc = WORKLOADS["plummer1M"]
+    saved = dict(PKW)
+    PKW.clear()
+    PKW.update(pkw)
+    PKW["kernel"] = KERNELS[args.kernel]
+    log(f"[bench] batched form: {desc}")
+    w = getattr(inputs, gen)()
+    lay = (tuple(w.grid), sv.layout(), sv.layout())
+    steps, warm = args.batched_steps, 2
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
+    r64 = run_timed(torch, sv, st, steps, warm)
+    st.close()
+    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP32, lay)
+    r32 = run_timed(torch, sv, st, steps, warm, graph=True)
+    st.close()
+    PKW.clear()
+    PKW.update(saved)
+    v64 = r64["pairs"] / (r64["ms_total"] / 1e3)
+    v32 = r32["pairs"] / (r32["ms_total"] / 1e3)
+    return {"workload": "plummer1M", "n": w.n, "steps": steps, "layout": "soa/tpiauto/branch",
+            "value": v32, "ms_per_step": r32["ms_total"] / steps, "flags": r32["flags"],
+            "fp64_eager": {"value": v64, "ms_per_step": r64["ms_total"] / steps, "flags": r64["flags"],
+                           "ms_density": r64["ms_density"], "ms_force": r64["ms_force"]},
+            "speedup_vs_fp64": v32 / v64}
 
 
 if __name__ == "__main__":
