@@ -257,6 +257,23 @@ size_t sphv_records_sort_workspace_bytes(uint32_t stride, int64_t n);
 int32_t sphv_records_sort(sphv_cells* c, void* aos_dev, uint32_t stride, void* ws_dev, size_t ws_bytes,
                           void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as sphv_records_sort, with the same kernels and results, but the
+ * sorted copy goes to a fixed device array of SPHV_RECORDS_SORT_STATIC_MAX_BYTES
+ * bytes that the library holds on each GPU it runs on until the process ends,
+ * instead of a caller workspace.  The call allocates nothing.
+ *   stride * n (n = the records c was built for) must not exceed the maximum,
+ *   else SPHV_E_WORKSPACE before anything is enqueued.
+ * Every call on one GPU shares that GPU's array, and the array keeps the last
+ * call's contents (every byte a call reads it wrote first): calls that overlap
+ * on one GPU (two streams, or two host threads) race and corrupt each other's
+ * records; order them on one stream.  The array's device address is looked up
+ * on the first call on each device (SPHV_E_HIP if that fails).  Other errors
+ * as sphv_records_sort. */
+#define SPHV_RECORDS_SORT_STATIC_MAX_BYTES (96ull << 20)
+int32_t sphv_records_sort_static(sphv_cells* c, void* aos_dev, uint32_t stride, void* stream);
+
 /* ----------------------------------------------------------------- views */
 
 enum {

@@ -526,6 +526,60 @@ int32_t sphv_records_sort(sphv_cells* c, void* aos, uint32_t stride, void* ws, s
     return SPHV_OK;
 }
 
+// ------------------------------------------- records sort without allocation
+//
+// The sorted copy of sphv_records_sort_static lives in one file-scope device
+// array per GPU.  In host code the array's name is only a stand-in for the
+// symbol: its device address is looked up once per device (with that device
+// current) and only that address is ever handed to kernels.
+
+static __device__ __align__(256) unsigned char scratch[SPHV_RECORDS_SORT_STATIC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array, or nullptr on a HIP error.
+void* scratch_of_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+int32_t sphv_records_sort_static(sphv_cells* c, void* aos, uint32_t stride, void* stream)
+{
+    if (!c || stride == 0 || stride % 4 || (uintptr_t)aos % 4) return SPHV_E_INVALID_ARG;
+    const int64_t n = c->dev.n;
+    if (n > 0 && !aos) return SPHV_E_INVALID_ARG;
+    if ((uint64_t)stride * (uint64_t)n > (uint64_t)SPHV_RECORDS_SORT_STATIC_MAX_BYTES) return SPHV_E_WORKSPACE;
+    if (!c->built) return SPHV_E_STATE;
+    {
+        const sphv_field last{stride - 4u, SPHV_ROLE_USER, SPHV_I32, SPHV_INOUT};
+        const sphv_descriptor dl{stride, 1, 0, &last};
+        if (int32_t r = check_records(aos, &dl, n)) return r;
+    }
+    void* ws = scratch_of_current_device();
+    if (!ws) return SPHV_E_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    // the same three kernels as sphv_records_sort, the copy in this device's array
+    if (launch_rec_move(aos, ws, c->dev.perm, nullptr, stride, n, s) != hipSuccess) return SPHV_E_HIP;
+    if (launch_rec_move(ws, aos, nullptr, nullptr, stride, n, s) != hipSuccess) return SPHV_E_HIP;
+    if (launch_sorted_index(c->dev.perm, c->dev.key, c->dev.key_sorted, n, s) != hipSuccess) return SPHV_E_HIP;
+    c->sorted = true;
+    return SPHV_OK;
+}
+
 int32_t sphv_cells_get_info(const sphv_cells* c, sphv_cells_info* out)
 {
     if (!c || !out) return SPHV_E_INVALID_ARG;

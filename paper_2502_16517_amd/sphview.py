@@ -40,7 +40,8 @@ EXPORTS = [
     "sphv_view_create", "sphv_aos_to_soa", "sphv_soa_to_aos", "sphv_view_field", "sphv_view_destroy",
     "sphv_sph_density", "sphv_sph_force", "sphv_step_reduce", "sphv_kick_drift", "sphv_graph_begin", "sphv_graph_end",
     "sphv_graph_launch", "sphv_graph_destroy", "sphv_autotune_candidates", "sphv_autotune_workspace_bytes",
-    "sphv_autotune", "sphv_records_sort_workspace_bytes", "sphv_records_sort", "sphv_grid_for",
+    "sphv_autotune", "sphv_records_sort_workspace_bytes", "sphv_records_sort", "sphv_records_sort_static",
+    "sphv_grid_for",
     "sphv_autotune_grid_workspace_bytes", "sphv_autotune_grid",
 ]
 
@@ -136,6 +137,7 @@ def lib():
                                       C.POINTER(Layout), C.POINTER(C.c_float), VP]),
         "sphv_records_sort_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_int64]),
         "sphv_records_sort": (C.c_int32, [VP, VP, C.c_uint32, VP, C.c_size_t, VP]),
+        "sphv_records_sort_static": (C.c_int32, [VP, VP, C.c_uint32, VP]),
         "sphv_grid_for": (C.c_int32, [C.POINTER(Params), C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
         "sphv_autotune_grid_workspace_bytes": (C.c_size_t, [C.POINTER(Descriptor), C.POINTER(Descriptor),
                                                             C.c_int64, C.POINTER(Params), C.c_int32,
@@ -323,6 +325,16 @@ def records_sort(cells, aos, stride: int, ws, stream=None, ws_bytes: int | None 
     """Moves the records into the cells' sorted order (whole records)."""
     nb = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 0)
     _chk(lib().sphv_records_sort(cells, _ptr(aos), stride, _ptr(ws), nb, _stream(stream)), "records_sort")
+
+
+# largest stride * n that sphv_records_sort_static takes (its fixed device array)
+RECORDS_SORT_STATIC_MAX_BYTES = 96 << 20
+
+
+def records_sort_static(cells, aos, stride: int, stream=None):
+    """records_sort without a workspace: the library's fixed per-GPU array
+    holds the copy (calls that overlap on one GPU race)."""
+    _chk(lib().sphv_records_sort_static(cells, _ptr(aos), stride, _stream(stream)), "records_sort_static")
 
 
 # ------------------------------------------------------------ views

@@ -302,6 +302,17 @@ def test_records_sort_workspace_and_errors():
         with pytest.raises(sv.SphvError) as e:
             sv.records_sort(cells, aos, stride, ws, ws_bytes=nb)
         assert e.value.status == status
+    # the static form: argument checks, then the size against its fixed array,
+    # then the state; no device work and no lookup of the array on these paths
+    big = (sv.RECORDS_SORT_STATIC_MAX_BYTES // 10 // 4 + 1) * 4
+    for stride, aos, status in ((6, fake, sv.E_INVALID_ARG), (256, fake + 2, sv.E_INVALID_ARG),
+                                (big, fake, sv.E_WORKSPACE), (256, fake, sv.E_STATE)):
+        with pytest.raises(sv.SphvError) as e:
+            sv.records_sort_static(cells, aos, stride)
+        assert e.value.status == status
+    with pytest.raises(sv.SphvError) as e:
+        sv.records_sort_static(None, fake, 256)
+    assert e.value.status == sv.E_INVALID_ARG
     sv.cells_destroy(cells)
     d = sv.density_descriptor()
     # a sorted view plans no storage, like the view over the records
