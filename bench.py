@@ -444,6 +444,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched form (FP32 pairs, graph replay) on the Plummer sphere")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--list-cap", type=int, default=0,
+                    help="neighbour-list capacity per particle: > 0 runs both pair loops as list walks "
+                         "(one lane per particle), 0 the item kernels over cell windows")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic kernel for "
                          "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -480,6 +483,7 @@ def main():
     gen, pkw, desc = WORKLOADS[args.workload]
     PKW.update(pkw)
     PKW["kernel"] = KERNELS[args.kernel]
+    PKW["list_cap"] = args.list_cap
     log(f"[bench] generating the workload: {desc}")
     w = getattr(inputs, gen)()
     if args.host_records:

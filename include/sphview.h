@@ -147,6 +147,10 @@ typedef struct {
     double headroom;   /* cell reach: R = ceil(2 h headroom / min cell), >= 1     */
     int32_t max_iter;  /* density passes, 1..64                                   */
     int32_t kernel;    /* smoothing kernel, SPHV_KERNEL_CUBIC or SPHV_KERNEL_QUARTIC */
+    int32_t list_cap;  /* 0: the pair loops walk cell windows per work item; 1..4096: */
+                       /* they walk per-particle neighbour lists of at most list_cap */
+                       /* entries (the cells workspace holds them; see below)       */
+    int32_t reserved;
 } sphv_params;
 
 /* Smoothing kernels W(r, h) = w(q) / (pi h^3), q = r/h, both with support
@@ -160,8 +164,20 @@ typedef struct {
  * takes parameters. */
 enum { SPHV_KERNEL_CUBIC = 0, SPHV_KERNEL_QUARTIC = 1 };
 
-/* Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16,
- * kernel SPHV_KERNEL_CUBIC. */
+/* Neighbour lists (list_cap > 0; the active set of each particle made explicit,
+ * paper Sec. 2.3).  One lane per particle.  The density loop first lists, in
+ * its window's order, every candidate within 2 h_l, h_l = min(h_cap,
+ * (1 + 1/16) h) at the h it starts from, then runs every Newton pass over
+ * that list; a particle whose h leaves h_l, or whose list would exceed
+ * list_cap, runs its remaining passes over the whole window instead (same
+ * candidates, same order).  The force loop lists exactly its pairs
+ * (r < 2 max(h_i, h_j) at the converged h) and evaluates them; a particle
+ * with more than list_cap pairs evaluates them from the window.  The layout's
+ * tpi and masked do not apply to list walks (every list entry is evaluated,
+ * out-of-range density entries as the neutral element).  The lists need
+ * list_cap * n * 4 bytes of the cells workspace.
+ * Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16,
+ * kernel SPHV_KERNEL_CUBIC, list_cap 0. */
 int32_t sphv_params_init(sphv_params* p, const double lo[3], const double len[3],
                          const int32_t grid[3], const int32_t periodic[3]);
 
@@ -228,6 +244,10 @@ typedef struct {
     int64_t max_items;
 } sphv_cells_info;
 
+/* The cells workspace also holds the force loops' per-particle constants
+ * (A = P/(Omega rho^2), c, 1/h, 1/(pi h^4), (2h)^2; 40 bytes per particle),
+ * which sphv_sph_force computes once per particle before its pairs, and with
+ * list_cap > 0 the neighbour lists. */
 size_t sphv_cells_workspace_bytes(int64_t n, const sphv_params* p);
 int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p,
                           void* ws_dev, size_t ws_bytes);

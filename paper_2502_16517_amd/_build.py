@@ -13,7 +13,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphview.so")
 ARCH = os.environ.get("SPHV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "tune.cpp", "k_cells.hip", "k_view.hip", "k_pair.hip"]
+SOURCES = ["abi.cpp", "tune.cpp", "k_cells.hip", "k_view.hip", "k_pair.hip", "k_list.hip"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -45,7 +45,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

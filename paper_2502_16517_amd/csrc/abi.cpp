@@ -17,6 +17,7 @@ using namespace sphv;
 namespace {
 
 constexpr uint64_t kAlign = 256;
+constexpr int32_t kMaxListCap = 4096;
 
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -97,7 +98,8 @@ bool finite_params(const sphv_params* p)
             return false;
     return std::isfinite(p->gamma) && p->gamma > 1.0 && p->eta > 0.0 && p->cfl > 0.0 &&
            p->h_tol >= 0.0 && p->headroom >= 1.0 && p->max_iter >= 1 && p->max_iter <= 64 &&
-           (p->kernel == SPHV_KERNEL_CUBIC || p->kernel == SPHV_KERNEL_QUARTIC);
+           (p->kernel == SPHV_KERNEL_CUBIC || p->kernel == SPHV_KERNEL_QUARTIC) && p->list_cap >= 0 &&
+           p->list_cap <= kMaxListCap;
 }
 
 Geom geom_of(const sphv_params* p)
@@ -240,7 +242,7 @@ Access acc_rec(const int32_t* index, uint64_t stride)
 }
 
 // Cells workspace carving (all arrays 256-B aligned).
-uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
+uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t list_cap)
 {
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) { char* p = base ? base + off : nullptr; off = align_up(off + bytes, kAlign); return p; };
@@ -268,6 +270,9 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc)
     c->pair_part = (int64_t*)take(8ull * kPartSlots * kMaxPairBlocks);
     c->scan_part = (int32_t*)take(4 * (uint64_t)scan_blocks);
     c->meta = (int32_t*)take(4 * META_SIZE);
+    c->list_cap = list_cap;
+    c->list = list_cap > 0 ? (int32_t*)take(4 * (uint64_t)list_cap * (uint64_t)std::max<int64_t>(n, 1)) : nullptr;
+    c->fconst = (double*)take(5 * 8 * (uint64_t)std::max<int64_t>(n, 1));
     c->n = n;
     c->nc = nc;
     c->max_items = max_items;
@@ -451,7 +456,7 @@ size_t sphv_cells_workspace_bytes(int64_t n, const sphv_params* p)
     if (!p || n < 0 || !finite_params(p)) return 0;
     int64_t nc = (int64_t)p->grid[0] * p->grid[1] * p->grid[2];
     CellsDev c{};
-    return (size_t)carve_cells(&c, nullptr, n, nc);
+    return (size_t)carve_cells(&c, nullptr, n, nc, p->list_cap);
 }
 
 int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p, void* ws, size_t ws_bytes)
@@ -464,11 +469,11 @@ int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p, voi
     if (nc > INT32_MAX / 2) return SPHV_E_UNSUPPORTED;
     if ((uintptr_t)ws % kAlign) return SPHV_E_WORKSPACE;
     CellsDev c{};
-    uint64_t need_b = carve_cells(&c, nullptr, n, nc);
+    uint64_t need_b = carve_cells(&c, nullptr, n, nc, p->list_cap);
     if (ws_bytes < need_b) return SPHV_E_WORKSPACE;
     sphv_cells* h = new (std::nothrow) sphv_cells;
     if (!h) return SPHV_E_INVALID_ARG;
-    carve_cells(&h->dev, (char*)ws, n, nc);
+    carve_cells(&h->dev, (char*)ws, n, nc, p->list_cap);
     h->params = *p;
     *out = h;
     return SPHV_OK;
@@ -807,6 +812,12 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     if (v->n == 0) return SPHV_OK;
     a.reach = c->dev.reach_d;
     a.qhead = META_QHEAD_D;
+    if (c->dev.list_cap > 0) {
+        a.list = c->dev.list;
+        a.list_cap = c->dev.list_cap;
+        return hip_status(launch_density_list(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
+                                              p->kernel, (hipStream_t)stream));
+    }
     return hip_status(launch_density(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
                                      (int)v->layout.masked, p->kernel, (hipStream_t)stream));
 }
@@ -840,6 +851,13 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
         e = launch_force_reach(c->dev, ref_rec(v->aos, hp.f), v->desc.stride, nullptr, a.g, (DevState*)state, st);
     }
     if (e != hipSuccess) return SPHV_E_HIP;
+    a.fconst = c->dev.fconst;
+    if (launch_force_prep(a, direct, v->precision == SPHV_PREC_FP32, st) != hipSuccess) return SPHV_E_HIP;
+    if (c->dev.list_cap > 0) {
+        a.list = c->dev.list;
+        a.list_cap = c->dev.list_cap;
+        return hip_status(launch_force_list(a, direct, v->precision == SPHV_PREC_FP32, p->kernel, st));
+    }
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, p->kernel, st));
 }
 

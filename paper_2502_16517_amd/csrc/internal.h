@@ -87,6 +87,10 @@ struct CellsDev {
     int64_t* pair_part;    // [kMaxPairBlocks][kPartSlots] per-wave counters of the last pair loop
     int32_t* scan_part;    // [scan blocks + 1]
     int32_t* meta;         // [META_SIZE]: item count, mask tag, force R_global, queue heads
+    int32_t* list;         // [list_cap][n] neighbour lists (list walks only, else null)
+    double* fconst;        // [5][n] per-particle force constants (of the pair precision)
+    int32_t list_cap;
+    int32_t pad_l;
     int64_t n;
     int64_t nc;
     int64_t max_items;
@@ -127,6 +131,10 @@ struct PairArgs {
     double* red_part;          // force: per reduction block partials
     int64_t n;
     double cfl;
+    int32_t* list;             // list walks: entry k of sorted position p at list[k n + p]
+    void* fconst;              // force: per-particle constants (R[5][n], R the pair precision)
+    int32_t list_cap;
+    int32_t pad3;
 };
 
 }  // namespace sphv
@@ -148,6 +156,12 @@ hipError_t launch_scatter(const FieldRef* src, const FieldRef* dst, int nf, cons
                           const Access& dst_acc, int64_t n, hipStream_t s);
 hipError_t launch_density(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
 hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int kernel, hipStream_t s);
+// the list walks (k_list.hip); each ends with the fold of its counters
+hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kernel, hipStream_t s);
+hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kernel, hipStream_t s);
+// per-particle constants of both force loops (k_list.hip), into a.fconst
+hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_t s);
+hipError_t launch_pair_fold(const PairArgs& a, int nblocks, int density, hipStream_t s);
 // in_view: in6 are members of the view (read with outacc) instead of the records
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,
                                const Access& outacc, int out_direct, int in_view, DevState* st,

@@ -1,0 +1,784 @@
+// Pair loops over per-particle neighbour lists (the list walk), an alternative
+// to the item kernels of k_pair.hip selected by sphv_params.list_cap > 0.
+//
+// Mapping onto gfx950: one lane per local particle i (view element p = sorted
+// position), 64 consecutive particles per wave, waves over the particles in a
+// grid-stride loop.  No LDS, no barriers: every lane is independent, so the
+// kernels hold many waves per SIMD to hide the latency of the candidate and
+// list loads, which the L1/L2 serve (neighbouring lanes read neighbouring
+// cells).
+//  * Build: the lane walks the active set of its particle -- the (2R+1)^3
+//    cells around its own cell (paper Sec. 2.3: local vs active particles) --
+//    in a fixed order (dz, dy, then the row's cells along x, wrapped part
+//    first) and appends every candidate within its list radius to its list
+//    (entry k of particle p at list[k n + p], so that a wave's k-th entries
+//    are one contiguous 256-byte run).
+//  * Evaluation: the lane walks its list in order, so every pair is evaluated
+//    with no divergence between lanes other than list lengths.
+//  * Density: one list (radius 2 h_l, h_l = min(h_cap, (1 + 1/16) h_0)) serves
+//    every Newton pass.  Should h leave h_l, or the list overflow its capacity,
+//    the lane evaluates its remaining passes over the whole window (the same
+//    candidates in the same order, so the same sums), without the list.
+//  * Force: the list holds exactly the pairs r < 2 max(h_i, h_j) at the
+//    converged h; a lane whose pairs overflow the list evaluates them in a
+//    second walk.  The per-particle constants that need a division or a root
+//    (A = P / (Omega rho^2), c, 1/h, the kernel norm) are computed once per
+//    particle by k_force_prep, not once per pair.
+//  * Periodic images: minimum-image differences on the FP64 positions; in FP32
+//    the candidate's cell-relative position is moved to the local cell's frame
+//    by the nearest-image cell offset, exactly as the item kernels stage it.
+//  * Every sum runs over the pairs in list (= window) order, so results are
+//    deterministic; the outputs do not depend on the layout of the view.
+#include <atomic>
+#include <type_traits>
+
+#include "k_common.h"
+
+namespace sphv {
+
+namespace {
+
+constexpr double kPiL = 3.14159265358979323846;
+constexpr double kGrowL = 1.0 + 1.0 / 16.0;   // list radius over the initial h
+
+__device__ __forceinline__ void neumaier_l(float& s, float& c, float x)
+{
+    float t = s + x;
+    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+// The smoothing kernels (truncated-power form, branch free; W = w(q)/(pi h^3)):
+// cubic M4 w = (2-q)_+^3/4 - (1-q)_+^3; quartic M5 w = k((2-q)_+^4 - 5(1.2-q)_+^4
+// + 10(0.4-q)_+^4), k = 15625/65536, its knots scaled to the support 2h.
+template <int KERN, class R>
+__device__ __forceinline__ void spl(R q, R& w, R& dw)
+{
+    const R a = fmax(R(2) - q, R(0));
+    if constexpr (KERN == SPHV_KERNEL_QUARTIC) {
+        const R b = fmax(R(1.2) - q, R(0));
+        const R c = fmax(R(0.4) - q, R(0));
+        const R a3 = a * a * a;
+        const R b3 = b * b * b;
+        const R c3 = c * c * c;
+        const R k = R(15625.0 / 65536.0);
+        w = k * fma(a3, a, fma(R(-5) * b3, b, R(10) * c3 * c));
+        dw = (R(-4) * k) * fma(R(-5), b3, fma(R(10), c3, a3));
+    } else {
+        const R b = fmax(R(1) - q, R(0));
+        const R a2 = a * a;
+        const R b2 = b * b;
+        w = fma(R(0.25) * a2, a, -(b2 * b));
+        dw = fma(R(3), b2, R(-0.75) * a2);
+    }
+}
+
+template <int KERN, class R>
+__device__ __forceinline__ R spl_dw(R q)
+{
+    const R a = fmax(R(2) - q, R(0));
+    if constexpr (KERN == SPHV_KERNEL_QUARTIC) {
+        const R b = fmax(R(1.2) - q, R(0));
+        const R c = fmax(R(0.4) - q, R(0));
+        const R k = R(15625.0 / 65536.0);
+        return (R(-4) * k) * fma(R(-5), b * b * b, fma(R(10), c * c * c, a * a * a));
+    } else {
+        const R b = fmax(R(1) - q, R(0));
+        return fma(R(3), b * b, R(-0.75) * (a * a));
+    }
+}
+
+// 1/sqrt(x) for normal x > 0: hardware estimate and Newton-Raphson steps
+// y <- y (3/2 - x y^2 / 2) (two in double, one in float).
+__device__ __forceinline__ double rsq_l(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ float rsq_l(float x)
+{
+    float y = __builtin_amdgcn_rsqf(x);
+    const float hx = 0.5f * x;
+    return y * fmaf(-hx, y * y, 1.5f);
+}
+
+// 1/d: hardware estimate and Newton-Raphson steps y <- y + y (1 - d y).
+__device__ __forceinline__ double rcp_l(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ float rcp_l(float d)
+{
+    float y = __builtin_amdgcn_rcpf(d);
+    return fmaf(y, fmaf(-d, y, 1.0f), y);
+}
+
+template <class R> struct TinyL;
+template <> struct TinyL<double> { static constexpr double v = 1e-300; };
+template <> struct TinyL<float> { static constexpr float v = 1e-30f; };
+
+// Per-axis reach of one particle's window (reach R of its cell), narrowed on a
+// periodic axis too short for 2R+1 cells (flagged).
+__device__ __forceinline__ void lane_reach(const Geom& g, int R, int r[3], uint32_t& flags)
+{
+    for (int d = 0; d < 3; ++d) {
+        r[d] = R;
+        if (g.periodic[d] && 2 * R + 1 > g.n[d]) {
+            r[d] = (g.n[d] - 1) / 2;
+            flags |= SPHV_F_GRID_TOO_SMALL;
+        }
+    }
+}
+
+// Minimum-image difference a - b along axis d: the nearest periodic image on
+// a periodic axis (within half a box length), the plain difference otherwise.
+__device__ __forceinline__ double mi_diff(double a, double b, const Geom& g, int d)
+{
+    double dx = a - b;
+    if (g.periodic[d]) {
+        const double half = 0.5 * g.len[d];
+        dx = dx > half ? dx - g.len[d] : (dx < -half ? dx + g.len[d] : dx);
+    }
+    return dx;
+}
+
+// Nearest-image cell offset k_j - k_i along axis d (|offset| <= n/2 on a
+// periodic axis; within a window of reach r <= (n-1)/2 it is the window's).
+__device__ __forceinline__ int mi_cell(int kj, int ki, const Geom& g, int d)
+{
+    int dk = kj - ki;
+    if (g.periodic[d]) {
+        const int n = g.n[d];
+        dk = 2 * dk > n ? dk - n : (2 * dk < -n ? dk + n : dk);
+    }
+    return dk;
+}
+
+// FP32 position member of element l along axis d, relative to the corner of
+// cell k_d: an FP32 view stores it so; a record's double is converted as the
+// gather converts it.
+template <class L>
+__device__ __forceinline__ float ld_rel(const FieldRef& f, const L& l, const Geom& g, int d, int k)
+{
+    if (f.dtype == SPHV_F32) return *(const float*)l.at(f);
+    const double v = *(const double*)l.at(f);
+    const double o = __dadd_rn(g.lo[d], __dmul_rn((double)k, g.cell[d]));
+    return __double2float_rn(__dsub_rn(v, o));
+}
+
+// Any other member as float (an FP32 view's float, or a double rounded).
+template <class L>
+__device__ __forceinline__ float ld_f32v(const FieldRef& f, const L& l)
+{
+    if (f.dtype == SPHV_F32) return *(const float*)l.at(f);
+    return __double2float_rn(*(const double*)l.at(f));
+}
+
+template <class R, class L>
+__device__ __forceinline__ R ld_r(const FieldRef& f, const L& l)
+{
+    if constexpr (std::is_same<R, float>::value) return ld_f32v(f, l);
+    else return ld_f64(f, l);
+}
+
+// Candidate position relative to the local particle's frame: FP64 absolute
+// (differences by minimum image), FP32 relative to the local cell's corner.
+template <bool DIRECT, bool FP32>
+struct Pos;
+
+template <bool DIRECT>
+struct Pos<DIRECT, false> {
+    double x, y, z;
+    __device__ __forceinline__ void load(const PairArgs& a, const Loc<DIRECT>& l, int, int, int)
+    {
+        x = ld_f64(a.f[SPHV_X], l);
+        y = ld_f64(a.f[SPHV_Y], l);
+        z = ld_f64(a.f[SPHV_Z], l);
+    }
+};
+
+template <bool DIRECT>
+struct Pos<DIRECT, true> {
+    float x, y, z;
+    // (ox, oy, oz): the candidate's nearest-image cell offset from the local cell
+    __device__ __forceinline__ void load(const PairArgs& a, const Loc<DIRECT>& l, int jx, int jy, int jz, int ox,
+                                         int oy, int oz)
+    {
+        x = ld_rel(a.f[SPHV_X], l, a.g, 0, jx) + __double2float_rn((double)ox * a.g.cell[0]);
+        y = ld_rel(a.f[SPHV_Y], l, a.g, 1, jy) + __double2float_rn((double)oy * a.g.cell[1]);
+        z = ld_rel(a.f[SPHV_Z], l, a.g, 2, jz) + __double2float_rn((double)oz * a.g.cell[2]);
+    }
+};
+
+// Squared distance between the local particle (xi, yi, zi) and candidate c,
+// and the components of x_i - x_j.
+template <bool FP32, class P, class R>
+__device__ __forceinline__ R diff(const PairArgs& a, R xi, R yi, R zi, const P& c, R& dx, R& dy, R& dz)
+{
+    if constexpr (FP32) {
+        dx = xi - c.x;
+        dy = yi - c.y;
+        dz = zi - c.z;
+    } else {
+        dx = mi_diff(xi, c.x, a.g, 0);
+        dy = mi_diff(yi, c.y, a.g, 1);
+        dz = mi_diff(zi, c.z, a.g, 2);
+    }
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Walks the window of cell (kx, ky, kz) with per-axis reach r in a fixed order
+// (dz, dy, then the row's cells along x: wrapped left part, main part, wrapped
+// right part) and calls visit(j, jx, jy, jz, ox, oy, oz) for every candidate j
+// (sorted position) of cell (jx, jy, jz), (ox, oy, oz) being that cell's
+// offset from the local cell in the window.
+template <class V>
+__device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], V&& visit)
+{
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    for (int dz = -r[2]; dz <= r[2]; ++dz) {
+        int z2 = kz + dz;
+        if (z2 < 0 || z2 >= nz) {
+            if (!a.g.periodic[2]) continue;
+            z2 += z2 < 0 ? nz : -nz;
+        }
+        for (int dy = -r[1]; dy <= r[1]; ++dy) {
+            int y2 = ky + dy;
+            if (y2 < 0 || y2 >= ny) {
+                if (!a.g.periodic[1]) continue;
+                y2 += y2 < 0 ? ny : -ny;
+            }
+            const int row = (z2 * ny + y2) * nx;
+            for (int dx = -r[0]; dx <= r[0]; ++dx) {
+                int x2 = kx + dx;
+                if (x2 < 0 || x2 >= nx) {
+                    if (!a.g.periodic[0]) continue;
+                    x2 += x2 < 0 ? nx : -nx;
+                }
+                const int jb = a.cell_start[row + x2];
+                const int je = a.cell_start[row + x2 + 1];
+                for (int j = jb; j < je; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+            }
+        }
+    }
+}
+
+// ================================================================ density
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    const double eta3 = a.eta * a.eta * a.eta;
+    if (blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 0;   // the item kernels' mask cache is not written
+    unsigned long long n_final = 0, n_evals = 0;
+    int maxit = 0;
+    uint32_t flags = 0;
+
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        const int cell = a.key_sorted[p];
+        int kx, ky, kz;
+        cell_coords(cell, a.g, kx, ky, kz);
+        int r[3];
+        lane_reach(a.g, a.reach[cell], r, flags);
+        double hcap = 0.5 * (double)r[0] * a.g.cell[0];
+        hcap = fmin(hcap, 0.5 * (double)r[1] * a.g.cell[1]);
+        hcap = fmin(hcap, 0.5 * (double)r[2] * a.g.cell[2]);
+        // a fused r^2 is a few ulp from the exact one: the list radius is widened
+        // so that it never drops a candidate the exact test would take
+        constexpr double kWiden = FP32 ? 1.0 + 4e-6 : 1.0 + 1e-12;
+
+        const Loc<DIRECT> li = locate<DIRECT>(a.acc, p);
+        R xi, yi, zi;
+        double mi;
+        if constexpr (FP32) {
+            xi = ld_rel(a.f[SPHV_X], li, a.g, 0, kx);
+            yi = ld_rel(a.f[SPHV_Y], li, a.g, 1, ky);
+            zi = ld_rel(a.f[SPHV_Z], li, a.g, 2, kz);
+            mi = (double)ld_f32v(a.f[SPHV_M], li);
+        } else {
+            xi = ld_f64(a.f[SPHV_X], li);
+            yi = ld_f64(a.f[SPHV_Y], li);
+            zi = ld_f64(a.f[SPHV_Z], li);
+            mi = ld_f64(a.f[SPHV_M], li);
+        }
+        const double h0 = ld_f64(a.f[SPHV_H], li);
+        const double hl = fmin(hcap, kGrowL * h0);
+        const R Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
+
+        // candidate j of the window, loaded and placed in the local frame
+        auto cand = [&](int j, int jx, int jy, int jz, int ox, int oy, int oz, R& cm) {
+            Pos<DIRECT, FP32> c;
+            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+            else c.load(a, lj, jx, jy, jz);
+            cm = ld_r<R>(a.f[SPHV_M], lj);
+            return c;
+        };
+
+        // ---- build: the candidates within the list radius, in window order
+        int32_t* L = a.list + p;
+        int len = 0;
+        walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+            Pos<DIRECT, FP32> c;
+            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+            else c.load(a, lj, jx, jy, jz);
+            R dx, dy, dz;
+            if constexpr (FP32) {
+                dx = xi - c.x;
+                dy = yi - c.y;
+                dz = zi - c.z;
+            } else {
+                dx = mi_diff(xi, c.x, a.g, 0);
+                dy = mi_diff(yi, c.y, a.g, 1);
+                dz = mi_diff(zi, c.z, a.g, 2);
+            }
+            if (fma(dz, dz, fma(dy, dy, dx * dx)) < Hl2w) {
+                if (len < cap) L[(int64_t)len * n] = j;
+                ++len;
+            }
+        });
+        bool lists = len <= cap;
+
+        // ---- passes of the h iteration
+        double h = h0;
+        unsigned long long it_evals = 0;
+        for (int pass = 0;; ++pass) {
+            const double hinv = 1.0 / h;
+            const R H2 = (R)((2.0 * h) * (2.0 * h));
+            const R hin = (R)hinv;
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0;       // sum m w, sum w, sum m (3w + q w')
+            float f0 = 0.f, f1 = 0.f, f2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+            R p0 = 0, p1 = 0, p2 = 0;
+            int kf = 0;
+            int cnt = 0;
+            // one candidate's contribution; out of range it is the neutral element
+            auto term = [&](R m, R r2, bool in) {
+                const R rr = r2 * rsq_l(fmax(r2, TinyL<R>::v));
+                const R q = rr * hin;
+                R w, dw;
+                spl<KERN>(q, w, dw);
+                w = in ? w : (R)0;
+                dw = in ? dw : (R)0;
+                p0 = fma(m, w, p0);
+                p1 = p1 + w;
+                p2 = fma(m, fma(q, dw, (R)3 * w), p2);
+                if constexpr (FP32) {
+                    // float partial sums folded into the compensated ones every 16 terms
+                    if (++kf == 16) {
+                        neumaier_l(f0, c0, p0);
+                        neumaier_l(f1, c1, p1);
+                        neumaier_l(f2, c2, p2);
+                        p0 = p1 = p2 = 0;
+                        kf = 0;
+                    }
+                }
+            };
+            if (lists && h <= hl) {
+                // the list walk: entry k at list[k n + p]; the next entry's index
+                // is read while the current one is evaluated
+                int jn = len > 0 ? L[0] : 0;
+                for (int e = 0; e < len; ++e) {
+                    const int j = jn;
+                    if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
+                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                    Pos<DIRECT, FP32> c;
+                    if constexpr (FP32) {
+                        int jx, jy, jz;
+                        cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
+                        c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1),
+                               mi_cell(jz, kz, a.g, 2));
+                    } else {
+                        c.load(a, lj, 0, 0, 0);
+                    }
+                    const R m = ld_r<R>(a.f[SPHV_M], lj);
+                    R dx, dy, dz;
+                    const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+                    const bool in = r2 < H2;
+                    term(m, r2, in);
+                    cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
+                }
+            } else {
+                lists = false;
+                // the whole window: every candidate the list would hold (while h
+                // stays within h_l, those are exactly the list's entries, in its
+                // order, so the FP32 partial sums are grouped as in the list walk)
+                // and every candidate in range at the current h
+                walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+                    R m;
+                    const auto c = cand(j, jx, jy, jz, ox, oy, oz, m);
+                    R dx, dy, dz;
+                    const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+                    const bool in = r2 < H2;
+                    if (in || fma(dz, dz, fma(dy, dy, dx * dx)) < Hl2w) {
+                        term(m, r2, in);
+                        cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
+                    }
+                });
+            }
+            if constexpr (FP32) {
+                neumaier_l(f0, c0, p0);
+                neumaier_l(f1, c1, p1);
+                neumaier_l(f2, c2, p2);
+                t0 = (double)f0 + (double)c0;
+                t1 = (double)f1 + (double)c1;
+                t2 = (double)f2 + (double)c2;
+            } else {
+                t0 = p0;
+                t1 = p1;
+                t2 = p2;
+            }
+            it_evals += (unsigned long long)cnt;
+
+            const double h3 = h * h * h;
+            const double norm = 1.0 / (kPiL * h3);
+            const double rho = norm * t0;
+            const double nsum = norm * t1;
+            const double drho = -(norm * hinv) * t2;
+            const double mq = mi * eta3;
+            const double f = rho - mq / h3;
+            const double fp = drho + 3.0 * mq / (h3 * h);
+            double hn;
+            if (fp > 0.0) {
+                hn = h - f / fp;
+                if (hn < 0.5 * h) hn = 0.5 * h;
+                if (hn > 2.0 * h) hn = 2.0 * h;
+            } else {
+                hn = a.eta * cbrt(mi / rho);
+            }
+            if (!isfinite(hn)) hn = a.eta * cbrt(mi / rho);
+            if (hn > hcap) {
+                hn = hcap;
+                flags |= SPHV_F_H_CAP_HIT;
+            }
+            const bool conv = fabs(hn - h) <= a.tol * h;
+            if (conv || pass + 1 >= a.max_iter) {
+                if (!conv) flags |= SPHV_F_H_NOT_CONVERGED;
+                const double omega = 1.0 + h / (3.0 * rho) * drho;
+                const double wcount = (4.0 * kPiL / 3.0) * (8.0 * h3) * nsum;
+                if (!(isfinite(rho) && isfinite(omega))) flags |= SPHV_F_NONFINITE_OUTPUT;
+                st_f64(a.f[SPHV_H], li, h);
+                st_f64(a.f[SPHV_RHO], li, rho);
+                st_f64(a.f[SPHV_OMEGA], li, omega);
+                st_f64(a.f[SPHV_WCOUNT], li, wcount);
+                n_final += (unsigned long long)cnt;
+                maxit = pass + 1 > maxit ? pass + 1 : maxit;
+                break;
+            }
+            h = hn;
+        }
+        n_evals += it_evals;
+    }
+
+    for (int off = 32; off > 0; off >>= 1) {
+        n_final += __shfl_xor(n_final, off, kWave);
+        n_evals += __shfl_xor(n_evals, off, kWave);
+        const int o = __shfl_xor(maxit, off, kWave);
+        maxit = o > maxit ? o : maxit;
+        flags |= __shfl_xor(flags, off, kWave);
+    }
+    if (lane == 0) {
+        int64_t* pp = a.part + (int64_t)blockIdx.x * kPartSlots;
+        pp[0] = (int64_t)n_final;
+        pp[1] = (int64_t)n_evals;
+        pp[2] = maxit;
+        pp[3] = flags;
+    }
+}
+
+// ================================================================== force
+
+// Per-particle constants of the force loop, once per particle: A = P/(Omega
+// rho^2) with P = (gamma-1) rho u, c = sqrt(gamma (gamma-1) u), 1/h, the
+// kernel gradient's norm 1/(pi h^4) and (2h)^2, at fconst[k n + p], k = 0..4,
+// in the pair precision (both force loops read them instead of deriving them
+// again for every pair or staged candidate).
+template <bool DIRECT, bool FP32>
+__global__ void k_force_prep(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const Loc<DIRECT> l = locate<DIRECT>(a.acc, p);
+    const R gm1 = (R)(a.gamma - 1.0);
+    const R ggm1 = (R)(a.gamma * (a.gamma - 1.0));
+    const R h = ld_r<R>(a.f[SPHV_H], l), rho = ld_r<R>(a.f[SPHV_RHO], l);
+    const R om = ld_r<R>(a.f[SPHV_OMEGA], l), u = ld_r<R>(a.f[SPHV_U], l);
+    const R P = gm1 * rho * u;
+    const R hv = (R)1 / h;
+    const R hv2 = hv * hv;
+    R* fc = (R*)a.fconst;
+    fc[p] = P / (om * rho * rho);
+    fc[a.n + p] = sqrt(ggm1 * u);
+    fc[2 * a.n + p] = hv;
+    fc[3 * a.n + p] = hv2 * hv2 / (R)kPiL;
+    const R H = (R)2 * h;
+    fc[4 * a.n + p] = H * H;
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    const R* fc = (const R*)a.fconst;
+    unsigned long long n_pairs = 0;
+    uint32_t flags = 0;
+
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        const int cell = a.key_sorted[p];
+        int kx, ky, kz;
+        cell_coords(cell, a.g, kx, ky, kz);
+        int r[3];
+        lane_reach(a.g, a.reach[cell], r, flags);
+
+        const Loc<DIRECT> li = locate<DIRECT>(a.acc, p);
+        R xi, yi, zi;
+        if constexpr (FP32) {
+            xi = ld_rel(a.f[SPHV_X], li, a.g, 0, kx);
+            yi = ld_rel(a.f[SPHV_Y], li, a.g, 1, ky);
+            zi = ld_rel(a.f[SPHV_Z], li, a.g, 2, kz);
+        } else {
+            xi = ld_f64(a.f[SPHV_X], li);
+            yi = ld_f64(a.f[SPHV_Y], li);
+            zi = ld_f64(a.f[SPHV_Z], li);
+        }
+        const R vxi = ld_r<R>(a.f[SPHV_VX], li), vyi = ld_r<R>(a.f[SPHV_VY], li), vzi = ld_r<R>(a.f[SPHV_VZ], li);
+        const R hi = ld_r<R>(a.f[SPHV_H], li), rhoi = ld_r<R>(a.f[SPHV_RHO], li);
+        const R hali = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], li);
+        const R Ai = fc[p], ci = fc[n + p], hinvi = fc[2 * n + p], normi = fc[3 * n + p];
+        const R Hi = (R)2 * hi;
+        const R H2i = Hi * Hi;
+
+        // ---- build: the pairs r < 2 max(h_i, h_j) (and coincident j != i), in window order
+        int32_t* L = a.list + p;
+        int len = 0;
+        int coinc = 0;   // coincident neighbours: counted as pairs, no force
+        auto pair_test = [&](int j, int jx, int jy, int jz, int ox, int oy, int oz, R& dx, R& dy, R& dz, R& r2,
+                             Loc<DIRECT>& lj) {
+            Pos<DIRECT, FP32> c;
+            lj = locate<DIRECT>(a.acc, j);
+            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+            else c.load(a, lj, jx, jy, jz);
+            r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+            return r2 < fmax(H2i, fc[4 * n + j]);
+        };
+        walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+            R dx, dy, dz, r2;
+            Loc<DIRECT> lj;
+            if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj)) {
+                if (r2 > (R)0) {
+                    if (len < cap) L[(int64_t)len * n] = j;
+                    ++len;
+                } else if (j != (int)p) {
+                    ++coinc;
+                }
+            }
+        });
+
+        double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0;
+        float fax = 0.f, cax = 0.f, fay = 0.f, cay = 0.f, faz = 0.f, caz = 0.f, fdu = 0.f, cdu = 0.f;
+        R pax = 0, pay = 0, paz = 0, pdu = 0;
+        int kf = 0;
+        R vsig = (R)2 * ci;
+        // one pair's contribution (r > 0)
+        auto term = [&](int j, const Loc<DIRECT>& lj, R dx, R dy, R dz, R r2) {
+            const R vxj = ld_r<R>(a.f[SPHV_VX], lj), vyj = ld_r<R>(a.f[SPHV_VY], lj), vzj = ld_r<R>(a.f[SPHV_VZ], lj);
+            const R mj = ld_r<R>(a.f[SPHV_M], lj), rhoj = ld_r<R>(a.f[SPHV_RHO], lj);
+            const R halj = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], lj);
+            const R Aj = fc[j], cj = fc[n + j], hinvj = fc[2 * n + j], normj = fc[3 * n + j];
+            const R y = rsq_l(r2);
+            const R rr = r2 * y;
+            const R gi = spl_dw<KERN>(rr * hinvi) * normi;
+            const R gj = spl_dw<KERN>(rr * hinvj) * normj;
+            const R gbar = (R)0.5 * (gi + gj);
+            const R ex = dx * y, ey = dy * y, ez = dz * y;
+            const R w = (vxi - vxj) * ex + (vyi - vyj) * ey + (vzi - vzj) * ez;
+            const R mu = w < (R)0 ? w : (R)0;
+            const R vs = ci + cj - (R)3 * mu;
+            // Pi = -(alpha_bar / 2) v_sig mu / rho_bar = -alpha_bar v_sig mu / (rho_i + rho_j)
+            const R visc = -(hali + halj) * vs * mu * rcp_l(rhoi + rhoj);
+            const R Agi = Ai * gi;
+            const R coef = mj * fma(visc, gbar, fma(Aj, gj, Agi));
+            const R dui = mj * fma((R)0.5 * visc, gbar, Agi) * w;
+            pax = fma(-coef, ex, pax);
+            pay = fma(-coef, ey, pay);
+            paz = fma(-coef, ez, paz);
+            pdu = pdu + dui;
+            vsig = vs > vsig ? vs : vsig;
+            if constexpr (FP32) {
+                if (++kf == 16) {
+                    neumaier_l(fax, cax, pax);
+                    neumaier_l(fay, cay, pay);
+                    neumaier_l(faz, caz, paz);
+                    neumaier_l(fdu, cdu, pdu);
+                    pax = pay = paz = pdu = 0;
+                    kf = 0;
+                }
+            }
+        };
+
+        if (len <= cap) {
+            int jn = len > 0 ? L[0] : 0;
+            for (int e = 0; e < len; ++e) {
+                const int j = jn;
+                if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                Pos<DIRECT, FP32> c;
+                if constexpr (FP32) {
+                    int jx, jy, jz;
+                    cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
+                    c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1),
+                           mi_cell(jz, kz, a.g, 2));
+                } else {
+                    c.load(a, lj, 0, 0, 0);
+                }
+                R dx, dy, dz;
+                const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+                term(j, lj, dx, dy, dz, r2);
+            }
+        } else {
+            // more pairs than the list holds: the same pairs in the same order, from the window
+            walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+                R dx, dy, dz, r2;
+                Loc<DIRECT> lj;
+                if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj) && r2 > (R)0)
+                    term(j, lj, dx, dy, dz, r2);
+            });
+        }
+        if constexpr (FP32) {
+            neumaier_l(fax, cax, pax);
+            neumaier_l(fay, cay, pay);
+            neumaier_l(faz, caz, paz);
+            neumaier_l(fdu, cdu, pdu);
+            ax = (double)fax + (double)cax;
+            ay = (double)fay + (double)cay;
+            az = (double)faz + (double)caz;
+            du = (double)fdu + (double)cdu;
+        } else {
+            ax = pax;
+            ay = pay;
+            az = paz;
+            du = pdu;
+        }
+        st_f64(a.f[SPHV_AX], li, ax);
+        st_f64(a.f[SPHV_AY], li, ay);
+        st_f64(a.f[SPHV_AZ], li, az);
+        st_f64(a.f[SPHV_UDT], li, du);
+        st_f64(a.f[SPHV_VSIG], li, (double)vsig);
+        n_pairs += (unsigned long long)(len + coinc);
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(du))) flags |= SPHV_F_NONFINITE_OUTPUT;
+    }
+
+    for (int off = 32; off > 0; off >>= 1) {
+        n_pairs += __shfl_xor(n_pairs, off, kWave);
+        flags |= __shfl_xor(flags, off, kWave);
+    }
+    if (lane == 0) {
+        int64_t* pp = a.part + (int64_t)blockIdx.x * kPartSlots;
+        pp[0] = (int64_t)n_pairs;
+        pp[1] = 0;
+        pp[2] = 0;
+        pp[3] = flags;
+    }
+}
+
+// Workgroups (one wave each) that the device holds at once for a kernel, a
+// multiple of the 8 XCDs, at most kMaxPairBlocks; queried once per kernel.
+template <class K>
+int list_blocks(K kernel, std::atomic<int>& cache, int64_t n)
+{
+    int v = cache.load(std::memory_order_relaxed);
+    if (v <= 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        v = per_cu * cus / kNumXcd * kNumXcd;
+        if (v < kNumXcd) v = kNumXcd;
+        if (v > kMaxPairBlocks) v = kMaxPairBlocks;
+        cache.store(v, std::memory_order_relaxed);
+    }
+    const int64_t need = (n + kWave - 1) / kWave;
+    return (int)(need < v ? (need > 0 ? need : 1) : v);
+}
+
+}  // namespace
+
+template <class K>
+static hipError_t run_list(K kernel, std::atomic<int>& cache, const PairArgs& a0, int density, hipStream_t s)
+{
+    PairArgs a = a0;
+    a.nblocks = list_blocks(kernel, cache, a.n);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_pair_fold(a, a.nblocks, density, s);
+}
+
+#define SPHV_LIST_CASE(KERNEL, D, F, DENS)                                                  \
+    do {                                                                                    \
+        if (kern == SPHV_KERNEL_QUARTIC) {                                                  \
+            static std::atomic<int> cache_q{0};                                             \
+            return run_list(KERNEL<D, F, SPHV_KERNEL_QUARTIC>, cache_q, a, DENS, s);        \
+        }                                                                                   \
+        static std::atomic<int> cache{0};                                                   \
+        return run_list(KERNEL<D, F, SPHV_KERNEL_CUBIC>, cache, a, DENS, s);                \
+    } while (0)
+
+hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kern, hipStream_t s)
+{
+    if (direct) {
+        if (fp32) SPHV_LIST_CASE(k_density_list, true, true, 1);
+        SPHV_LIST_CASE(k_density_list, true, false, 1);
+    }
+    if (fp32) SPHV_LIST_CASE(k_density_list, false, true, 1);
+    SPHV_LIST_CASE(k_density_list, false, false, 1);
+}
+
+hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((a.n + 255) / 256);
+    if (direct) {
+        if (fp32) hipLaunchKernelGGL((k_force_prep<true, true>), dim3(nb), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_force_prep<true, false>), dim3(nb), dim3(256), 0, s, a);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_force_prep<false, true>), dim3(nb), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_force_prep<false, false>), dim3(nb), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kern, hipStream_t s)
+{
+    if (direct) {
+        if (fp32) SPHV_LIST_CASE(k_force_list, true, true, 0);
+        SPHV_LIST_CASE(k_force_list, true, false, 0);
+    }
+    if (fp32) SPHV_LIST_CASE(k_force_list, false, true, 0);
+    SPHV_LIST_CASE(k_force_list, false, false, 0);
+}
+
+}  // namespace sphv

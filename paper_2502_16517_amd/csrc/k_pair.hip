@@ -258,6 +258,15 @@ struct RawK {
 template <class T> using Raw4 = RawK<T, 4>;
 template <class T> using Raw12 = RawK<T, 12>;
 
+// Raw members of one staged force candidate and its per-particle constants.
+template <class T, class R>
+struct ForceRaw {
+    T v[9];
+    R fc[5];
+    int j, ix, iy, iz, key;
+    uint64_t mask;
+};
+
 template <class T, class L>
 __device__ __forceinline__ T ld_raw(const FieldRef& f, const L& l)
 {
@@ -1092,8 +1101,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         // the density loop's masks apply, this lane's mask of the chunk), put
         // converts them, derives P, c, A, 1/h, and writes this lane's LDS slot
         uint64_t cmask = 0;
+        // the per-particle constants (A, c, 1/h, norm, (2h)^2), computed once per
+        // particle by the prep kernel that runs before this one
+        const R* fcon = (const R*)a.fconst;
         auto fetch = [&](bool valid, int j, int ix, int iy, int iz, int c) {
-            Raw12<RawT> v;
+            ForceRaw<RawT, R> v;
             v.j = j;
             v.ix = ix;
             v.iy = iy;
@@ -1102,15 +1114,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
             if (reuse && c < kMaskChunks) v.mask = a.item_masks[((int64_t)item * kMaskChunks + c) * kWave + lane];
             if (valid) {
                 const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                const int roles[12] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_M, SPHV_ALPHA,
-                                       SPHV_H, SPHV_RHO, SPHV_OMEGA, SPHV_U};
+                const int roles[9] = {SPHV_X, SPHV_Y, SPHV_Z, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_M, SPHV_ALPHA,
+                                      SPHV_RHO};
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v.v[k] = ld_raw<RawT>(a.f[roles[k]], lj);
+                for (int k = 0; k < 9; ++k) v.v[k] = ld_raw<RawT>(a.f[roles[k]], lj);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) v.fc[k] = fcon[(int64_t)k * a.n + j];
                 if constexpr (FP32) v.key = a.key_sorted[j];
             }
             return v;
         };
-        auto put = [&](const Raw12<RawT>& v, bool in_chunk) {
+        auto put = [&](const ForceRaw<RawT, R>& v, bool in_chunk) {
             cmask = v.mask;
             if (!in_chunk) return;
             if constexpr (FP32) {
@@ -1131,17 +1145,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
             svz[lane] = (R)v.v[5];
             sm[lane] = (R)v.v[6];
             sal[lane] = (R)0.5 * (R)v.v[7];
-            const R h_ = (R)v.v[8], rho_ = (R)v.v[9], om_ = (R)v.v[10], u_ = (R)v.v[11];
-            const R P_ = gm1 * rho_ * u_;
-            const R hv = (R)1 / h_;
-            const R hv2 = hv * hv;
-            const R H_ = (R)2 * h_;
-            sH2[lane] = H_ * H_;
-            shinv[lane] = hv;
-            snorm[lane] = hv2 * hv2 / (R)kPi;
-            srho[lane] = rho_;
-            sA[lane] = P_ / (om_ * rho_ * rho_);
-            sc[lane] = sqrt(ggm1 * u_);
+            srho[lane] = (R)v.v[8];
+            sA[lane] = v.fc[0];
+            sc[lane] = v.fc[1];
+            shinv[lane] = v.fc[2];
+            snorm[lane] = v.fc[3];
+            sH2[lane] = v.fc[4];
             sj[lane] = v.j;
         };
         auto stage = [&](int j, int ix, int iy, int iz) { put(fetch(true, j, ix, iy, iz, kMaskChunks), true); };
@@ -1492,6 +1501,13 @@ __global__ __launch_bounds__(kFoldThreads) void k_pair_fold(int32_t* meta, int q
         st->flags |= c3;
     }
     if (t < kNumXcd) meta[qhead + t * kQStride] = 0;
+}
+
+hipError_t launch_pair_fold(const PairArgs& a, int nblocks, int density, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair_fold, dim3(1), dim3(kFoldThreads), 0, s, a.meta, a.qhead, (const int64_t*)a.part,
+                       nblocks, a.state, density);
+    return hipGetLastError();
 }
 
 int pair_grid_blocks(int64_t max_items)

@@ -59,7 +59,8 @@ class Params(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3), ("cell", C.c_double * 3),
                 ("inv_cell", C.c_double * 3), ("grid", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
                 ("gamma", C.c_double), ("eta", C.c_double), ("cfl", C.c_double), ("h_tol", C.c_double),
-                ("headroom", C.c_double), ("max_iter", C.c_int32), ("kernel", C.c_int32)]
+                ("headroom", C.c_double), ("max_iter", C.c_int32), ("kernel", C.c_int32),
+                ("list_cap", C.c_int32), ("reserved", C.c_int32)]
 
 
 class State(C.Structure):
@@ -726,6 +727,152 @@ class Stepper:
         if getattr(self, "cells", None):
             cells_destroy(self.cells)
         self.v_dens = self.v_force = self.cells = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# every physics member of a record: the state a persistent view keeps in SoA
+# across steps (all of it read and written by some step of the loop)
+STATE_FIELDS = [(name, INOUT) for name in ("x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "ax", "ay", "az",
+                                           "m", "h", "rho", "omega", "u", "uh", "u_dt", "alpha", "v_sig",
+                                           "wcount")]
+
+
+class PersistentStepper:
+    """The particle state kept in SoA across loops and steps (the paper's
+    future work: a larger member set held in SoA instead of converted per loop).
+
+    One view over every physics member of the records (STATE_FIELDS, SoA,
+    FP64 storage) is opened once, in the cell order of a first cells_build,
+    and stays open: its storage is the state.  Each step runs, through the
+    C-ABI, cells_build on the storage's own x, y, z, h; the density and force
+    loops over views of the storage (default: loops directly on it through the
+    cells' perm, so no member is copied); the step reduction; kick_drift on the
+    storage.  The records are written only by flush() (the view's scatter, then
+    a new gather) and close(); until then their physics members are temporarily
+    invalid (paper Sec. 3.2) and the alias rule keeps other views off them.
+    precision: FP64 or FP32 pair arithmetic (the storage stays FP64);
+    layout_density / layout_force: layouts of the loop views over the storage
+    (SPHV_LAYOUT_DIRECT: no copy; SoA / AoSoA: gathered from the storage in
+    cell order each step)."""
+
+    def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
+                 layout_density: Layout | None = None, layout_force: Layout | None = None, device="cuda",
+                 aos=None, stream=None):
+        import torch
+        self.torch = torch
+        self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
+        self.p = params
+        self.precision = precision
+        self.stream = stream
+        self.device = device
+        self.ld = layout_density or layout(LAYOUT_DIRECT)
+        self.lf = layout_force or layout(LAYOUT_DIRECT)
+        if aos is None:
+            aos = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(rec))).to(device)
+        self.aos = aos
+        u8 = dict(dtype=torch.uint8, device=device)
+        n = self.n
+        self.state = torch.zeros(state_bytes(), **u8)
+        state_init(self.state, stream)
+        # the records' cells, once: the order the storage starts in
+        self.cells_ws = torch.empty(max(256, cells_workspace_bytes(n, params)), **u8)
+        self.cells = cells_create(n, params, self.cells_ws)
+        cells_build(self.cells, self.aos, cells_descriptor(), self.state, stream)
+        self.index = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        if n:
+            # the perm copied out of the cells workspace (every build rewrites it)
+            off = cells_get_info(self.cells).perm - self.cells_ws.data_ptr()
+            self.index.view(torch.uint8)[:4 * n].copy_(self.cells_ws[off:off + 4 * n])
+        self.d_state = descriptor(_rec_fields(STATE_FIELDS))
+        lay = layout(LAYOUT_SOA)
+        self.ws_state = torch.empty(max(256, view_workspace_bytes(self.d_state, n, lay, PREC_FP64)), **u8)
+        self.v_state = view_create(self.d_state, n, lay, PREC_FP64, self.aos, self.index, self.ws_state)
+        aos_to_soa(self.v_state, None, stream)
+        # the storage as a struct-of-arrays store: member k at its own array
+        base = self.ws_state.data_ptr()
+        self.base = base
+        offs = {}
+        for k, (name, _) in enumerate(STATE_FIELDS):
+            ptr, dt, bl, bb = view_field(self.v_state, k) if n else (base + 8 * k, F64, 0, 0)
+            offs[name] = ptr - base
+
+        def store_desc(spec):
+            return descriptor([(nm, offs[nm], F64, acc) for nm, acc in spec], stride=8)
+
+        self.d_cells = store_desc(CELLS_FIELDS)
+        self.d_dens = store_desc(DENSITY_FIELDS)
+        self.d_force = store_desc(FORCE_FIELDS)
+        self.d_kick = store_desc(KICK_FIELDS)
+        self.perm_ptr = cells_get_info(self.cells).perm
+        self.v_dens = self.v_force = None
+        self._make_views()
+
+    def _make_views(self):
+        u8 = dict(dtype=self.torch.uint8, device=self.device)
+        n = self.n
+        self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_dens, n, self.ld, self.precision)), **u8)
+        self.v_dens = view_create(self.d_dens, n, self.ld, self.precision, self.base, self.perm_ptr, self.ws_dens)
+        self.ws_force = self.torch.empty(max(256, view_workspace_bytes(self.d_force, n, self.lf, self.precision)),
+                                         **u8)
+        self.v_force = view_create(self.d_force, n, self.lf, self.precision, self.base, self.perm_ptr,
+                                   self.ws_force)
+
+    # the pieces of a step, in order
+    def build(self):
+        begin_step(self.state, self.stream)
+        cells_build(self.cells, self.base, self.d_cells, self.state, self.stream)
+
+    def density(self):
+        aos_to_soa(self.v_dens, self.cells, self.stream)
+        sph_density(self.v_dens, self.cells, self.p, self.state, self.stream)
+        soa_to_aos(self.v_dens, self.stream)
+
+    def force(self):
+        aos_to_soa(self.v_force, self.cells, self.stream)
+        sph_force(self.v_force, self.cells, self.p, self.state, self.stream)
+        step_reduce(self.v_force, self.p, self.state, self.stream)
+        soa_to_aos(self.v_force, self.stream)
+
+    def kick(self):
+        kick_drift(self.base, self.d_kick, self.n, self.p, self.state, self.stream)
+
+    def step(self):
+        self.build()
+        self.density()
+        self.force()
+        self.kick()
+
+    def read_state(self) -> State:
+        return read_state(self.state, self.stream)
+
+    def flush(self):
+        """Writes the state back to the records (the view's scatter) and opens
+        the view again (a new gather, same order): the records hold the
+        current state afterwards."""
+        soa_to_aos(self.v_state, self.stream)
+        aos_to_soa(self.v_state, None, self.stream)
+
+    def records(self) -> np.ndarray:
+        self.flush()
+        self.torch.cuda.synchronize()
+        return self.aos.cpu().numpy().view(np.float64).reshape(self.n, inputs.NSLOT).copy()
+
+    def close(self):
+        """Writes the state back to the records and releases the views."""
+        if getattr(self, "v_state", None):
+            for v in (self.v_dens, self.v_force):
+                if v:
+                    view_destroy(v)
+            soa_to_aos(self.v_state, self.stream)
+            self.torch.cuda.synchronize()
+            view_destroy(self.v_state)
+            cells_destroy(self.cells)
+        self.v_state = self.v_dens = self.v_force = self.cells = None
 
     def __del__(self):
         try:

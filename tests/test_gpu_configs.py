@@ -1,0 +1,221 @@
+"""GPU parity on the benchmark workloads at their full sizes, beyond one step:
+the FP32 form on the Plummer sphere (2^20 particles, cells of 1 to ~2000) and
+on the 256^3 shear layer, against the FP64 oracle on sampled particles; twenty
+steps of the full two-state tube with every layout, eager and graph-replayed;
+a hundred CFL-limited steps of the 256^3 shear layer (momentum conserved to
+roundoff, energy drift bounded); records in pinned host memory against the
+oracle.  Item kernels and list walks alike."""
+import numpy as np
+import pytest
+
+from paper_2502_16517_amd import inputs
+from paper_2502_16517_amd import sphview as sv
+
+from gpu_helpers import S, bits, check_density, check_force, cols, oracle_density, oracle_force
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CAP = 128
+
+WALKS = {"items": 0, "lists": CAP}
+
+FULL32 = {
+    "plummer1M": (lambda: inputs.config4(), {"headroom": 1.6}),
+    "kh256": (lambda: inputs.config5(), {}),
+}
+
+
+def _sampled_check(orc, w, dens, out, tol_d, tol_f, seed):
+    idx = np.sort(np.random.default_rng(seed).choice(w.n, size=400, replace=False))
+    c = cols(w.rec)
+    box = orc.box_of(w.lo, w.length, w.periodic)
+    rd = orc.density(c["x"], c["y"], c["z"], c["m"], c["h"], box, w.eta, targets=idx)
+    wd = check_density(dens, rd, idx=idx, tol=tol_d)
+    dc = cols(dens)
+    rf = orc.force(dc["x"], dc["y"], dc["z"], dc["vx"], dc["vy"], dc["vz"], dc["m"], dc["h"], dc["rho"],
+                   dc["omega"], dc["u"], dc["alpha"], box, inputs.GAMMA, targets=idx)
+    wf = check_force(out, rf, idx=idx, tol=tol_f, vsig_tol=max(tol_f * 1e-2, 1e-14))
+    return wd, wf
+
+
+def _one_step(w, precision, **pkw):
+    p = sv.params_for(w, **pkw)
+    if precision == sv.PREC_FP32:
+        p.h_tol = 1e-6
+    st = sv.Stepper(w.rec, p, precision)
+    st.build()
+    st.density()
+    dens = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    return dens, out, state
+
+
+@pytest.mark.parametrize("walk", list(WALKS))
+@pytest.mark.parametrize("name", list(FULL32))
+def test_fp32_full_size_sampled(orc, name, walk):
+    """The FP32 form at full size: 400 sampled particles within 1e-5 (density
+    fields) and 1e-4 (force fields) of the FP64 oracle."""
+    print(f"[fp32 full] {name} {walk}", flush=True)
+    mk, pkw = FULL32[name]
+    w = mk()
+    dens, out, state = _one_step(w, sv.PREC_FP32, list_cap=WALKS[walk], **pkw)
+    assert state.flags & ~sv.F_OUT_OF_BOX == 0, state.flags
+    wd, wf = _sampled_check(orc, w, dens, out, 1e-5, 1e-4, seed=3)
+    print(name, walk, "fp32 density", wd, "force", wf, flush=True)
+
+
+FULL64 = {
+    "tube64": (lambda: inputs.config2(), {}),
+    "kh128": (lambda: inputs.config3(), {}),
+    "plummer1M": (lambda: inputs.config4(), {"headroom": 1.6}),
+    "kh256": (lambda: inputs.config5(), {}),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL64))
+def test_list_walk_full_size_sampled_parity(orc, name):
+    """The list walks at the workloads' full sizes (the benchmark's launch
+    configuration): 400 sampled particles against the oracle, FP64 bound."""
+    print(f"[list full] {name}", flush=True)
+    mk, pkw = FULL64[name]
+    w = mk()
+    dens, out, state = _one_step(w, sv.PREC_FP64, list_cap=CAP, **pkw)
+    assert state.flags & ~sv.F_OUT_OF_BOX == 0, state.flags
+    wd, wf = _sampled_check(orc, w, dens, out, 1e-12, 1e-12, seed=4)
+    print(name, "lists density", wd, "force", wf, flush=True)
+
+
+TUBE_LAYOUTS = {
+    "soa": sv.layout(sv.LAYOUT_SOA),
+    "aosoa8": sv.layout(sv.LAYOUT_AOSOA, 8),
+    "direct": sv.layout(sv.LAYOUT_DIRECT),
+    "sorted": sv.layout(sv.LAYOUT_SORTED),
+}
+
+
+def _tube_run(w, cap, lay, graph):
+    s = torch.cuda.Stream()
+    st = sv.Stepper(w.rec, sv.params_for(w, list_cap=cap), layout_density=lay, layout_force=lay, stream=s)
+    if graph:
+        sv.graph_begin(s)
+        st.step()
+        g = sv.graph_end(s)
+        junk = torch.zeros(1 << 16, device="cuda")
+        for _ in range(20):
+            sv.graph_launch(g, s)
+            junk.add_(1.0)
+            torch.cuda.synchronize()
+        sv.graph_destroy(g)
+    else:
+        for _ in range(20):
+            st.step()
+    rec, state = st.records(), st.read_state()
+    st.close()
+    assert state.flags == 0 and state.nstep == 20, state.flags
+    return rec, state
+
+
+@pytest.mark.parametrize("walk", list(WALKS))
+def test_full_tube_twenty_steps_layouts_eager_and_graph(walk):
+    """Twenty steps of the full two-state tube (294,912 particles).  SoA and
+    AoSoA views and loops on the records give bit-identical records, eager and
+    replayed from a captured graph.  Records moved into cell order after each
+    build (the sorted layout) keep the particles of a cell in the previous
+    step's order, so from the second step on sums run in another order: its
+    eager and graph runs are bit-identical, and it follows the others to
+    rounding (compared particle by particle through the id member)."""
+    w = inputs.config2()
+    cap = WALKS[walk]
+    ref = None
+    runs = {}
+    for name, lay in TUBE_LAYOUTS.items():
+        for graph in (False, True):
+            print(f"[tube 20 steps] {walk} {name} graph={graph}", flush=True)
+            rec, state = _tube_run(w, cap, lay, graph)
+            runs[(name, graph)] = (rec, state)
+            if name == "sorted":
+                continue
+            if ref is None:
+                ref = (rec, state)
+                continue
+            assert np.array_equal(bits(rec), bits(ref[0])), (name, graph)
+            assert state.dt == ref[1].dt and tuple(state.sums) == tuple(ref[1].sums), (name, graph)
+    (se, sse), (sg, ssg) = runs[("sorted", False)], runs[("sorted", True)]
+    assert np.array_equal(bits(se), bits(sg))
+    assert sse.dt == ssg.dt and tuple(sse.sums) == tuple(ssg.sums)
+    ids = lambda r: inputs.int_slot(r, "id")
+    a = se[np.argsort(ids(se), kind="stable")]
+    b = ref[0][np.argsort(ids(ref[0]), kind="stable")]
+    assert np.array_equal(ids(a), ids(b))
+    assert abs(sse.dt / ref[1].dt - 1) < 1e-10
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "rho"):
+        scale = np.max(np.abs(b[:, S[k]])) + 1e-300
+        err = np.max(np.abs(a[:, S[k]] - b[:, S[k]])) / scale
+        print(f"sorted vs views after 20 steps, {k}: {err:.2e}", flush=True)
+        assert err <= 1e-9, k
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_FP64, sv.PREC_FP32])
+def test_kh256_hundred_steps_conservation(precision):
+    """The full run: 100 CFL-limited steps of the 256^3 shear layer (list
+    walks).  The total momentum (not zero: the dense band moves one way) stays
+    at its first value to roundoff of sum |m v| every step, since the pair
+    forces are antisymmetric; the total energy drifts by less than 1e-3 (the
+    scheme conserves it up to its time-stepping error); no flag is raised."""
+    w = inputs.config5()
+    p = sv.params_for(w, list_cap=CAP)
+    if precision == sv.PREC_FP32:
+        p.h_tol = 1e-6
+    st = sv.Stepper(w.rec, p, precision)
+    mv = np.abs(w.rec[:, S["m"]][:, None] * w.rec[:, [S["vx"], S["vy"], S["vz"]]]).sum(axis=0)
+    scale = float(mv.sum())
+    E = []
+    P0 = None
+    worst_p = 0.0
+    for k in range(100):
+        st.step()
+        s = st.read_state()
+        assert s.flags == 0, (k, s.flags)
+        E.append(s.sums[3])
+        if P0 is None:
+            P0 = [s.sums[d] for d in range(3)]
+        worst_p = max(worst_p, max(abs(s.sums[d] - P0[d]) for d in range(3)) / scale)
+        if k % 10 == 0:
+            print(f"[kh256 100 steps] prec={precision} step {k} dt={s.dt:.3e} E={s.sums[3]:.12e} "
+                  f"|P|/sum|mv|={worst_p:.2e}", flush=True)
+    st.close()
+    drift = abs(E[-1] / E[0] - 1)
+    print(f"kh256 prec={precision}: momentum {worst_p:.2e} of sum |m v|, energy drift {drift:.2e}", flush=True)
+    # FP32 pair terms are rounded per side, so their antisymmetry holds to
+    # float rounding only
+    bound = 1e-12 if precision == sv.PREC_FP64 else 1e-6
+    assert worst_p < bound
+    assert drift < 1e-3
+
+
+@pytest.mark.parametrize("walk", list(WALKS))
+def test_pinned_host_records_match_oracle(orc, walk):
+    """Records in pinned host memory: one step (density, force) against the
+    oracle, not against the device-resident path."""
+    w = inputs.two_state_tube(16, 31)
+    raw = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(w.rec))).pin_memory()
+    p = sv.params_for(w, list_cap=WALKS[walk])
+    st = sv.Stepper(None, p, aos=raw)
+    st.build()
+    st.density()
+    dens = st.records()
+    st.force()
+    out = st.records()
+    state = st.read_state()
+    st.close()
+    assert state.flags == 0
+    ref = oracle_density(orc, w)
+    check_density(dens, ref, tol=1e-12)
+    assert state.pairs_density == int(ref["count"].sum())
+    rf = oracle_force(orc, w, dens)
+    check_force(out, rf, tol=1e-12, vsig_tol=1e-14)
+    assert state.pairs_force == int(rf["count"].sum())
