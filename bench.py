@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--tune-grid", action="store_true",
                     help="let the tuner pick the grid too (it times one snapshot of the particles; over the "
                          "timed steps the generated grid did better on this workload)")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the extra timing of the state kept in SoA across steps")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched form (FP32 pairs, graph replay) on the Plummer sphere")
     ap.add_argument("--batched-steps", type=int, default=5)
@@ -623,6 +625,12 @@ def main():
     d4["kick_drift"] = {"t_lower_ms": t_lower(n * BYTES_FP64["kick_drift"]), "t_ms": r64["ms_kick_drift"],
                         "frac": t_lower(n * BYTES_FP64["kick_drift"]) / r64["ms_kick_drift"]}
 
+    persistent = None
+    if not args.no_persistent:
+        log("[bench] fp64 eager, state kept in SoA across steps")
+        persistent = persistent_form(torch, sv, inputs, w, args)
+        persistent["speedup_vs_views"] = ms_step / persistent["ms_per_step"]
+
     batched = None
     if not args.no_batched:
         batched = batched_form(torch, sv, inputs, args)
@@ -663,6 +671,8 @@ def main():
         "other_kernel": other,
         # one view over both loops (gather before density, scatter after the reduction)
         "merged_view": merged,
+        # the state in SoA across steps: no conversion inside a step
+        "persistent_state": persistent,
         "conversions": conv,
         "reduce_ms": r64["ms_reduce"],
         "cells_build_ms": r64["ms_cells"],
@@ -677,6 +687,51 @@ def main():
     out["hbm_frac_step"] = algo_bytes / (ms_step / 1e3) / HBM_PEAK
     out["hbm_frac_span"] = algo_bytes / (r64["ms_span"] / 1e3) / HBM_PEAK
     print(json.dumps(out), flush=True)
+
+
+def persistent_form(torch, sv, inputs, w, args):
+    """The state kept in SoA across loops and steps (PersistentStepper): one
+    gather of every physics member before the timed steps, then per step
+    cells_build on the storage, the density and force loops directly on it
+    (through the cells' perm, no copy), the step reduction and kick_drift on
+    it.  The records are written back after the timed steps."""
+    s = torch.cuda.current_stream()
+    p = sv.params_init(w.lo, w.length, tuple(w.grid), w.periodic)
+    p.eta = w.eta
+    for k, v in PKW.items():
+        setattr(p, k, v)
+    st = sv.PersistentStepper(w.rec, p, stream=s)
+    for _ in range(args.warmup):
+        st.step()
+    torch.cuda.synchronize()
+    before = st.read_state()
+    names = ("start", "built", "dens", "force", "kicked")
+    ev = [{k: torch.cuda.Event(enable_timing=True) for k in names} for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k in range(args.steps):
+        e = ev[k]
+        e["start"].record(s)
+        st.build()
+        e["built"].record(s)
+        st.density()
+        e["dens"].record(s)
+        st.force()
+        e["force"].record(s)
+        st.kick()
+        e["kicked"].record(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    after = st.read_state()
+    st.close()
+    ms = e0.elapsed_time(e1)
+    span = lambda a, b: sum(x[a].elapsed_time(x[b]) for x in ev) / args.steps
+    return {"value": (after.pairs_total - before.pairs_total) / (ms / 1e3), "ms_per_step": ms / args.steps,
+            "ms_cells": span("start", "built"), "ms_density": span("built", "dens"),
+            "ms_force_and_reduce": span("dens", "force"), "ms_kick_drift": span("force", "kicked"),
+            "layout": "direct on the SoA state (no per-loop copy)", "flags": after.flags,
+            "conversion_bytes_per_step": 0,
+            "open_close_bytes": 2 * 22 * 8 * w.n}
 
 
 def batched_form(torch, sv, inputs, args):

@@ -120,11 +120,28 @@ typedef struct {
  *  - struct of arrays: stride equals the member size and members are whole
  *    arrays of n elements that do not overlap (offset >= previous + n*size).
  * Members must be naturally aligned and must not overlap; a role may appear
- * at most once. */
+ * at most once.
+ *
+ * flags = SPHV_DESC_RECORD_POINTERS: the records are scattered, reached through
+ * a list of their addresses (paper Sec. 5.1: the particles of a cell held as a
+ * list of pointers, and generic kernels over such lists).  The aos_dev of every
+ * call taking this descriptor is then the device address of an array of n
+ * uint64_t record addresses, record i's member f living at ptrs[i] +
+ * fields[f].offset (array-of-structs shape, stride the record size, each
+ * record aligned to 8 bytes).  cells_build, views of kind SOA, AOSOA and DIRECT
+ * (gather, loops, step reduction, scatter) and kick_drift accept it; views of
+ * kind SORTED, sphv_autotune and sphv_autotune_grid fail with
+ * SPHV_E_UNSUPPORTED (to move such records into cell order, permute the
+ * address list instead; sphv_records_sort moves contiguous records only).
+ * The address list itself is checked like records (device-addressable); the
+ * records it names are the caller's: each must be device-addressable and they
+ * must not overlap.  The alias rule of open views compares address lists:
+ * views through different lists are taken to name different records. */
+enum { SPHV_DESC_RECORD_POINTERS = 1u };
 typedef struct {
     uint64_t stride;
     uint32_t n_fields;
-    uint32_t reserved;
+    uint32_t flags;     /* 0, or SPHV_DESC_RECORD_POINTERS */
     const sphv_field* fields;
 } sphv_descriptor;
 

@@ -39,6 +39,9 @@ int32_t check_descriptor(const sphv_descriptor* d, int64_t n, int role_field[SPH
     if (d->n_fields > (uint32_t)kMaxFields) return SPHV_E_DESCRIPTOR;
     if (d->n_fields && !d->fields) return SPHV_E_INVALID_ARG;
     if (d->stride == 0) return SPHV_E_DESCRIPTOR;
+    if (d->flags & ~(uint32_t)SPHV_DESC_RECORD_POINTERS) return SPHV_E_DESCRIPTOR;
+    // records reached by address: array-of-structs shape, 8-byte aligned records
+    if ((d->flags & SPHV_DESC_RECORD_POINTERS) && d->stride % 8) return SPHV_E_DESCRIPTOR;
     for (int r = 0; r < SPHV_NROLES; ++r) role_field[r] = -1;
     bool aos = true;
     for (uint32_t k = 0; k < d->n_fields; ++k) {
@@ -54,6 +57,7 @@ int32_t check_descriptor(const sphv_descriptor* d, int64_t n, int role_field[SPH
         }
         if (f.offset + sz > d->stride) aos = false;
     }
+    if (!aos && (d->flags & SPHV_DESC_RECORD_POINTERS)) return SPHV_E_DESCRIPTOR;
     if (aos) {
         for (uint32_t k = 0; k < d->n_fields; ++k) {
             uint32_t sz = dtype_size(d->fields[k].dtype);
@@ -81,6 +85,8 @@ int32_t check_descriptor(const sphv_descriptor* d, int64_t n, int role_field[SPH
 
 uint64_t record_span(const sphv_descriptor* d, int64_t n)
 {
+    // records reached by address: the span of the address list
+    if (d->flags & SPHV_DESC_RECORD_POINTERS) return 8 * (uint64_t)std::max<int64_t>(n, 0);
     uint64_t hi = 0;
     for (uint32_t k = 0; k < d->n_fields; ++k) {
         uint64_t sz = dtype_size(d->fields[k].dtype);
@@ -207,10 +213,14 @@ FieldRef ref_view(const sphv_view* v, const FieldPlan& p)
     return r;
 }
 
-FieldRef ref_rec(char* aos, const sphv_field& f)
+bool by_pointer(const sphv_descriptor& d) { return (d.flags & SPHV_DESC_RECORD_POINTERS) != 0; }
+
+// A member of the records: base + offset of record 0, or (records reached by
+// address) a null base to which each record's address is added.
+FieldRef ref_rec(char* aos, const sphv_field& f, const sphv_descriptor& d)
 {
     FieldRef r;
-    r.base = aos;
+    r.base = by_pointer(d) ? nullptr : aos;
     r.off = f.offset;
     r.size = dtype_size(f.dtype);
     r.dtype = f.dtype;
@@ -230,14 +240,15 @@ Access acc_view(const sphv_view* v)
     return a;
 }
 
-Access acc_rec(const int32_t* index, uint64_t stride)
+Access acc_rec(const int32_t* index, const sphv_descriptor& d, const void* aos)
 {
     Access a{};
     a.lw = 0;
     a.mask = 0;
     a.block_bytes = 0;
     a.index = index;
-    a.stride = stride;
+    a.stride = d.stride;
+    a.ptrs = by_pointer(d) ? (const uint64_t*)aos : nullptr;
     return a;
 }
 
@@ -490,9 +501,9 @@ int32_t sphv_cells_build(sphv_cells* c, const void* aos, const sphv_descriptor* 
     FieldRef f[4];
     for (int k = 0; k < 4; ++k) {
         if (rf[roles[k]] < 0 || d->fields[rf[roles[k]]].dtype != SPHV_F64) return SPHV_E_DESCRIPTOR;
-        f[k] = ref_rec((char*)aos, d->fields[rf[roles[k]]]);
+        f[k] = ref_rec((char*)aos, d->fields[rf[roles[k]]], *d);
     }
-    Access rec = acc_rec(nullptr, d->stride);
+    Access rec = acc_rec(nullptr, *d, aos);
     Geom g = geom_of(&c->params);
     c->sorted = false;
     hipError_t e = launch_cells_build(c->dev, f, rec, g, (DevState*)state, (hipStream_t)stream);
@@ -628,6 +639,8 @@ int32_t sphv_view_create(sphv_view** out, const sphv_descriptor* d, int64_t n, c
     if (!v) return SPHV_E_INVALID_ARG;
     st = check_descriptor(d, n, v->role_field);
     if (st) { delete v; return st; }
+    // the sorted layout needs records moved into cell order: contiguous ones only
+    if ((d->flags & SPHV_DESC_RECORD_POINTERS) && l->kind == SPHV_LAYOUT_SORTED) { delete v; return SPHV_E_UNSUPPORTED; }
     v->fields.assign(d->fields, d->fields + d->n_fields);
     v->desc = *d;
     v->desc.fields = v->fields.data();
@@ -687,12 +700,12 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     int nf = 0;
     for (const FieldPlan& p : v->plan) {
         if (!(p.f.access & SPHV_IN)) continue;     // A_out \ A_in needs no preparation
-        src[nf] = ref_rec(v->aos, p.f);
+        src[nf] = ref_rec(v->aos, p.f, v->desc);
         dst[nf] = ref_view(v, p);
         ++nf;
     }
     if (!nf) return SPHV_OK;
-    Access sa = acc_rec(v->index, v->desc.stride);
+    Access sa = acc_rec(v->index, v->desc, v->aos);
     Access da = acc_view(v);
     Geom g{};
     const int32_t* key = nullptr;
@@ -718,12 +731,12 @@ int32_t sphv_soa_to_aos(sphv_view* v, void* stream)
     for (const FieldPlan& p : v->plan) {
         if (!(p.f.access & SPHV_OUT)) continue;    // only A_out goes back
         src[nf] = ref_view(v, p);
-        dst[nf] = ref_rec(v->aos, p.f);
+        dst[nf] = ref_rec(v->aos, p.f, v->desc);
         ++nf;
     }
     if (!nf) return SPHV_OK;
     Access sa = acc_view(v);
-    Access da = acc_rec(v->index, v->desc.stride);
+    Access da = acc_rec(v->index, v->desc, v->aos);
     return hip_status(launch_scatter(src, dst, nf, sa, da, v->n, (hipStream_t)stream));
 }
 
@@ -767,7 +780,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
     for (int r = 1; r < SPHV_NROLES; ++r) {
         int k = v->role_field[r];
         if (k < 0) continue;
-        a->f[r] = direct ? ref_rec(v->aos, v->plan[k].f) : ref_view(v, v->plan[k]);
+        a->f[r] = direct ? ref_rec(v->aos, v->plan[k].f, v->desc) : ref_view(v, v->plan[k]);
     }
     if (direct && v->precision == SPHV_PREC_FP32) {
         // FP32 loops over the records convert positions on the fly, exactly as
@@ -776,7 +789,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
         a->f[SPHV_Y].rel_axis = 1;
         a->f[SPHV_Z].rel_axis = 2;
     }
-    a->acc = direct ? acc_rec(sorted ? nullptr : v->index, v->desc.stride) : acc_view(v);
+    a->acc = direct ? acc_rec(sorted ? nullptr : v->index, v->desc, v->aos) : acc_view(v);
     a->g = geom_of(p);
     a->items = c->dev.items;
     a->cell_start = c->dev.cell_start;
@@ -848,7 +861,8 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
         const Access va = acc_view(v);
         e = launch_force_reach(c->dev, ref_view(v, hp), 0, &va, a.g, (DevState*)state, st);
     } else {
-        e = launch_force_reach(c->dev, ref_rec(v->aos, hp.f), v->desc.stride, nullptr, a.g, (DevState*)state, st);
+        e = launch_force_reach(c->dev, ref_rec(v->aos, hp.f, v->desc), v->desc.stride, nullptr, a.g, (DevState*)state, st,
+                               by_pointer(v->desc) ? (const uint64_t*)v->aos : nullptr);
     }
     if (e != hipSuccess) return SPHV_E_HIP;
     a.fconst = c->dev.fconst;
@@ -884,13 +898,13 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
     FieldRef in6[6], out5[5];
     for (int k = 0; k < 6; ++k) {
         const FieldPlan& fp = v->plan[v->role_field[rin[k]]];
-        in6[k] = in_view ? ref_view(v, fp) : ref_rec(v->aos, fp.f);
+        in6[k] = in_view ? ref_view(v, fp) : ref_rec(v->aos, fp.f, v->desc);
     }
     for (int k = 0; k < 5; ++k) {
         const FieldPlan& fp = v->plan[v->role_field[rout[k]]];
-        out5[k] = direct ? ref_rec(v->aos, fp.f) : ref_view(v, fp);
+        out5[k] = direct ? ref_rec(v->aos, fp.f, v->desc) : ref_view(v, fp);
     }
-    Access ra = acc_rec(v->index, v->desc.stride);
+    Access ra = acc_rec(v->index, v->desc, v->aos);
     Access oa = direct ? ra : acc_view(v);
     return hip_status(launch_force_reduce(in6, ra, out5, oa, direct, in_view, (DevState*)state, p->cfl, v->n,
                                           v->red_part, (hipStream_t)stream));
@@ -913,10 +927,10 @@ int32_t sphv_kick_drift(void* aos, const sphv_descriptor* d, int64_t n, const sp
     for (int k = 0; k < 15; ++k) {
         int i = rf[roles[k]];
         if (i < 0 || d->fields[i].dtype != SPHV_F64) return SPHV_E_DESCRIPTOR;
-        f[k] = ref_rec((char*)aos, d->fields[i]);
+        f[k] = ref_rec((char*)aos, d->fields[i], *d);
     }
     if (n == 0) return SPHV_OK;
-    return hip_status(launch_kick_drift(f, acc_rec(nullptr, d->stride), geom_of(p), (const DevState*)state, n,
+    return hip_status(launch_kick_drift(f, acc_rec(nullptr, *d, aos), geom_of(p), (const DevState*)state, n,
                                         (hipStream_t)stream));
 }
 
@@ -991,6 +1005,11 @@ bool device_addressable(const void* p)
 int32_t check_records(const void* aos, const sphv_descriptor* d, int64_t n)
 {
     if (n <= 0 || !d || !aos) return SPHV_OK;
+    if (d->flags & SPHV_DESC_RECORD_POINTERS) {
+        // the address list (the records it names are the caller's)
+        const char* b = (const char*)aos;
+        return device_addressable(b) && device_addressable(b + 8 * (uint64_t)n - 1) ? SPHV_OK : SPHV_E_INVALID_ARG;
+    }
     uint64_t end = 0;
     for (uint32_t k = 0; k < d->n_fields; ++k) {
         const uint64_t e = d->fields[k].offset + (uint64_t)(n - 1) * d->stride + dtype_size(d->fields[k].dtype);

@@ -55,6 +55,7 @@ struct Access {
     uint64_t block_bytes; // view
     const int32_t* index; // direct
     uint64_t stride;      // direct
+    const uint64_t* ptrs; // direct, records by address: record r at ptrs[r] (the members' base is null)
 };
 
 // Grid geometry passed to kernels.
@@ -148,7 +149,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* xyzh, const Acc
 // h from the records (through perm, stride bytes apart), or from a view (view_acc
 // not null: element p of the view is sorted position p)
 hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Access* view_acc,
-                              const Geom& g, DevState* st, hipStream_t s);
+                              const Geom& g, DevState* st, hipStream_t s, const uint64_t* rec_ptrs = nullptr);
 hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const Access& src_acc,
                          const Access& dst_acc, const int32_t* cell_key, const Geom& g, int64_t n,
                          hipStream_t s);

@@ -106,17 +106,18 @@ __device__ __forceinline__ void bin_one(const double c[3], double h, const Geom&
 }
 
 __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,
-                      uint64_t stride, Geom g, int64_t n, int32_t* key, int32_t* counts,
+                      uint64_t stride, const uint64_t* ptrs, Geom g, int64_t n, int32_t* key, int32_t* counts,
                       uint32_t* hmax_bits, DevState* st)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t rb = (uint64_t)i * stride;
+    const uint64_t rb = ptrs ? ptrs[i] : (uint64_t)i * stride;
+    auto at = [&](const FieldRef& f) { return (const double*)((uintptr_t)f.base + f.off + rb); };
     double c[3];
-    c[0] = *(const double*)(fx.base + fx.off + rb);
-    c[1] = *(const double*)(fy.base + fy.off + rb);
-    c[2] = *(const double*)(fz.base + fz.off + rb);
-    const double h = *(const double*)(fh.base + fh.off + rb);
+    c[0] = *at(fx);
+    c[1] = *at(fy);
+    c[2] = *at(fz);
+    const double h = *at(fh);
     int kk;
     uint32_t hb;
     bin_one(c, h, g, st, kk, hb);
@@ -597,7 +598,7 @@ __global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, 
 // into meta[rslot] (one atomic per block of 1024 cells).
 template <bool VIEW>
 __global__ void k_force_hbits(const int32_t* perm, const int32_t* key_sorted, FieldRef h, uint64_t stride,
-                              Access vacc, int64_t n, uint32_t* hbits)
+                              const uint64_t* ptrs, Access vacc, int64_t n, uint32_t* hbits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < n;
@@ -608,7 +609,8 @@ __global__ void k_force_hbits(const int32_t* perm, const int32_t* key_sorted, Fi
         if constexpr (VIEW)
             v = ld_f64(h, locate<false>(vacc, p));
         else
-            v = *(const double*)(h.base + h.off + (uint64_t)perm[p] * stride);
+            v = *(const double*)((uintptr_t)h.base + h.off +
+                                 (ptrs ? ptrs[perm[p]] : (uint64_t)perm[p] * stride));
         b = __float_as_uint(__double2float_ru(2.0 * v));
         k = key_sorted[p];
     }
@@ -729,12 +731,13 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
         return e;
     if (c.n > 0) {
         StagePlan sp;
-        if (!rec.index && plan_stage(f, 4, 0u, rec.stride, &sp))
+        if (!rec.index && !rec.ptrs && plan_stage(f, 4, 0u, rec.stride, &sp))
             hipLaunchKernelGGL(k_bin_staged, dim3(nblk(c.n, kStageThreads)), dim3(kStageThreads),
                                kStageThreads * sp.nch * 16, s, f[0], f[1], f[2], f[3], sp, rec.stride, g, c.n, c.key,
                                c.counts, c.hmax_bits, st);
         else
-            hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride, g,
+            hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride,
+                               rec.ptrs, g,
                                c.n, c.key, c.counts, c.hmax_bits, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -765,7 +768,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
 }
 
 hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t stride, const Access* view_acc,
-                              const Geom& g, DevState* st, hipStream_t s)
+                              const Geom& g, DevState* st, hipStream_t s, const uint64_t* rec_ptrs)
 {
     // hmax_f and the largest own reach start at zero with cells_build and only
     // grow: a later force call on larger h widens the windows, never narrows them
@@ -773,10 +776,10 @@ hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t str
     if (c.n > 0) {
         if (view_acc)
             hipLaunchKernelGGL(k_force_hbits<true>, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h,
-                               stride, *view_acc, c.n, c.hmax_f);
+                               stride, rec_ptrs, *view_acc, c.n, c.hmax_f);
         else
             hipLaunchKernelGGL(k_force_hbits<false>, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.perm, c.key_sorted, h,
-                               stride, Access{}, c.n, c.hmax_f);
+                               stride, rec_ptrs, Access{}, c.n, c.hmax_f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_f,

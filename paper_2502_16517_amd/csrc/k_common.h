@@ -20,8 +20,11 @@ struct Loc<false> {
 
 template <>
 struct Loc<true> {
-    uint64_t rb;
-    __device__ __forceinline__ char* at(const FieldRef& f) const { return f.base + f.off + rb; }
+    uint64_t rb;   // record byte offset from the members' base, or the record's address (base null)
+    __device__ __forceinline__ char* at(const FieldRef& f) const
+    {
+        return (char*)((uintptr_t)f.base + f.off + rb);
+    }
 };
 
 template <bool DIRECT>
@@ -41,7 +44,7 @@ __device__ __forceinline__ Loc<true> locate<true>(const Access& a, int64_t p)
 {
     Loc<true> l;
     int64_t r = a.index ? (int64_t)a.index[p] : p;
-    l.rb = (uint64_t)r * a.stride;
+    l.rb = a.ptrs ? a.ptrs[r] : (uint64_t)r * a.stride;
     return l;
 }
 

@@ -1613,7 +1613,7 @@ hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const Fie
     if (in_view && !out_direct) {
         // inputs and outputs in the view: the staged kernel's order, nothing staged
         hipLaunchKernelGGL((k_reduce_staged<false, true>), dim3((unsigned)nb), dim3(kStageThreads), 0, s, r, sp);
-    } else if (n > 0 && plan_stage(r.in, 6, 0u, r.rec.stride, &sp)) {
+    } else if (n > 0 && !r.rec.ptrs && plan_stage(r.in, 6, 0u, r.rec.stride, &sp)) {
         const size_t lds = kStageThreads * sp.nch * 16;
         if (out_direct)
             hipLaunchKernelGGL((k_reduce_staged<true, false>), dim3((unsigned)nb), dim3(kStageThreads), lds, s, r,

@@ -137,14 +137,14 @@ __device__ __forceinline__ void kick_one(Ptr&& P, const Geom& g, double dt, doub
     *P(12) = __dadd_rn(uh, __dmul_rn(du, half));
 }
 
-__global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint64_t stride, Geom g,
-                                                             const DevState* st, int64_t n)
+__global__ __launch_bounds__(kConvThreads) void k_kick_drift(KickFields kf, uint64_t stride, const uint64_t* ptrs,
+                                                             Geom g, const DevState* st, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double dt = st->dt;
-    const uint64_t rb = (uint64_t)i * stride;
-    auto P = [&](int k) -> double* { return (double*)(kf.f[k].base + kf.f[k].off + rb); };
+    const uint64_t rb = ptrs ? ptrs[i] : (uint64_t)i * stride;
+    auto P = [&](int k) -> double* { return (double*)((uintptr_t)kf.f[k].base + kf.f[k].off + rb); };
     kick_one(P, g, dt, __dmul_rn(0.5, dt), __dmul_rn(0.5, st->dt_prev), st->nstep <= 1);
 }
 
@@ -244,7 +244,7 @@ hipError_t launch_gather(const FieldRef* src, const FieldRef* dst, int nf, const
         fp.dst[k] = dst[k];
     }
     StagePlan sp;
-    if (n > 0 && nf > 0 && plan_stage(fp.src, nf, 0u, sa.stride, &sp))
+    if (n > 0 && nf > 0 && !sa.ptrs && plan_stage(fp.src, nf, 0u, sa.stride, &sp))
         hipLaunchKernelGGL(k_gather_staged, dim3((unsigned)((n + kStageThreads - 1) / kStageThreads)),
                            dim3(kStageThreads), kStageThreads * sp.nch * 16, s, fp, nf, sp, sa, da, cell_key, g, n);
     else
@@ -274,12 +274,13 @@ hipError_t launch_kick_drift(const FieldRef* f, const Access& rec, const Geom& g
     for (int k = 0; k < 15; ++k) kf.f[k] = f[k];
     // written: x y z vx vy vz vhx vhy vhz u uh (members 0-8, 12, 13)
     StagePlan sp;
-    if (n > 0 && !rec.index && plan_stage(kf.f, 15, 0x31FFu, rec.stride, &sp)) {
+    if (n > 0 && !rec.index && !rec.ptrs && plan_stage(kf.f, 15, 0x31FFu, rec.stride, &sp)) {
         const unsigned blocks = (unsigned)((n + kStageThreads - 1) / kStageThreads);
         hipLaunchKernelGGL(k_kick_staged, dim3(blocks), dim3(kStageThreads), kStageThreads * sp.nch * 16, s, kf, sp,
                            rec.stride, g, st, n);
     } else {
-        hipLaunchKernelGGL(k_kick_drift, dim3(nblk(n)), dim3(kConvThreads), 0, s, kf, rec.stride, g, st, n);
+        hipLaunchKernelGGL(k_kick_drift, dim3(nblk(n)), dim3(kConvThreads), 0, s, kf, rec.stride, rec.ptrs, g, st,
+                           n);
     }
     return hipGetLastError();
 }

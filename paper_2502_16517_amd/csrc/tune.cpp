@@ -240,6 +240,7 @@ int32_t sphv_autotune(int32_t loop, void* aos, const sphv_descriptor* d, const s
 {
     if (loop != SPHV_LOOP_DENSITY && loop != SPHV_LOOP_FORCE) return SPHV_E_INVALID_ARG;
     if (!d || !cells || !p || !best || reps < 1 || reps > 100) return SPHV_E_INVALID_ARG;
+    if (d->flags & SPHV_DESC_RECORD_POINTERS) return SPHV_E_UNSUPPORTED;
     sphv_cells_info info;
     int32_t st = sphv_cells_get_info(cells, &info);
     if (st) return st;
@@ -378,6 +379,7 @@ int32_t sphv_autotune_grid(void* aos, const sphv_descriptor* d_density, const sp
 {
     if (!d_density || !d_force || !p || !l_density || !l_force || !grids || !best || n < 0) return SPHV_E_INVALID_ARG;
     if (reps < 1 || reps > 100 || n_grids < 1 || n_grids > kMaxGrids) return SPHV_E_INVALID_ARG;
+    if ((d_density->flags | d_force->flags) & SPHV_DESC_RECORD_POINTERS) return SPHV_E_UNSUPPORTED;
     if (n > 0 && !aos) return SPHV_E_INVALID_ARG;
     if (l_density->kind == SPHV_LAYOUT_SORTED || l_force->kind == SPHV_LAYOUT_SORTED) return SPHV_E_UNSUPPORTED;
     const size_t need_b = sphv_autotune_grid_workspace_bytes(d_density, d_force, n, p, precision, l_density,

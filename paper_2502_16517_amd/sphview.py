@@ -27,6 +27,7 @@ IN, OUT, INOUT = 1, 2, 3
 LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT, LAYOUT_SORTED = 0, 1, 2, 3
 PREC_FP64, PREC_FP32 = 0, 1
 KERNEL_CUBIC, KERNEL_QUARTIC = 0, 1
+DESC_RECORD_POINTERS = 1
 LOOP_DENSITY, LOOP_FORCE = 0, 1
 
 ROLES = ["user", "x", "y", "z", "vx", "vy", "vz", "vhx", "vhy", "vhz", "ax", "ay", "az", "m", "h", "rho",
@@ -51,7 +52,7 @@ class Field(C.Structure):
 
 
 class Descriptor(C.Structure):
-    _fields_ = [("stride", C.c_uint64), ("n_fields", C.c_uint32), ("reserved", C.c_uint32),
+    _fields_ = [("stride", C.c_uint64), ("n_fields", C.c_uint32), ("flags", C.c_uint32),
                 ("fields", C.POINTER(Field))]
 
 
@@ -185,8 +186,9 @@ def _stream(stream) -> int | None:
 
 # ------------------------------------------------------------ descriptors
 
-def descriptor(fields, stride: int = inputs.STRIDE):
-    """fields: iterable of (role name or None, offset bytes, dtype, access)."""
+def descriptor(fields, stride: int = inputs.STRIDE, flags: int = 0):
+    """fields: iterable of (role name or None, offset bytes, dtype, access);
+    flags: DESC_RECORD_POINTERS for records reached through an address list."""
     fl = list(fields)
     arr = (Field * max(1, len(fl)))()
     for k, (role, off, dt, acc) in enumerate(fl):
@@ -194,13 +196,17 @@ def descriptor(fields, stride: int = inputs.STRIDE):
         arr[k].role = ROLE[role] if role else 0
         arr[k].dtype = dt
         arr[k].access = acc
-    d = Descriptor(stride, len(fl), 0, C.cast(arr, C.POINTER(Field)))
+    d = Descriptor(stride, len(fl), flags, C.cast(arr, C.POINTER(Field)))
     d._keep = arr
     return d
 
 
 def _rec_fields(spec):
     return [(name, inputs.SLOT[name] * 8, F64, acc) for name, acc in spec]
+
+
+def _rec_descriptor(spec, flags=0):
+    return descriptor(_rec_fields(spec), flags=flags)
 
 
 DENSITY_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("m", IN), ("h", INOUT), ("rho", OUT), ("omega", OUT),
@@ -219,24 +225,24 @@ MERGED_FIELDS = [("x", IN), ("y", IN), ("z", IN), ("vx", IN), ("vy", IN), ("vz",
                  ("ay", OUT), ("az", OUT), ("u_dt", OUT), ("v_sig", OUT)]
 
 
-def density_descriptor():
-    return descriptor(_rec_fields(DENSITY_FIELDS))
+def density_descriptor(flags=0):
+    return _rec_descriptor(DENSITY_FIELDS, flags)
 
 
-def force_descriptor():
-    return descriptor(_rec_fields(FORCE_FIELDS))
+def force_descriptor(flags=0):
+    return _rec_descriptor(FORCE_FIELDS, flags)
 
 
-def kick_descriptor():
-    return descriptor(_rec_fields(KICK_FIELDS))
+def kick_descriptor(flags=0):
+    return _rec_descriptor(KICK_FIELDS, flags)
 
 
-def cells_descriptor():
-    return descriptor(_rec_fields(CELLS_FIELDS))
+def cells_descriptor(flags=0):
+    return _rec_descriptor(CELLS_FIELDS, flags)
 
 
-def merged_descriptor():
-    return descriptor(_rec_fields(MERGED_FIELDS))
+def merged_descriptor(flags=0):
+    return _rec_descriptor(MERGED_FIELDS, flags)
 
 
 def soa_descriptor(spec, n: int, base_slots=None):
@@ -496,17 +502,25 @@ class Stepper:
     into cell order after each cells_build).  sort_records: move the records
     into cell order after each cells_build (implied by a SORTED layout).  aos
     may be an (n*256,) uint8 device tensor holding 256-byte records, or None to
-    upload ``rec``.  merged: one view over both loops (MERGED_FIELDS, FP64,
+    upload ``rec``.  record_ptrs: a device uint64 tensor of n record addresses
+    (records reached through an address list, DESC_RECORD_POINTERS): every
+    call then takes the list, and ``aos`` must be the buffer the records live
+    in (records() reads them back in list order).  merged: one view over both loops (MERGED_FIELDS, FP64,
     layout_density), gathered before the density loop and scattered after the
     force loop, so the density's outputs never leave the view in between.
     """
 
     def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
                  layout_density: Layout | None = None, layout_force: Layout | None = None,
-                 device="cuda", aos=None, stream=None, sort_records: bool = False, merged: bool = False):
+                 device="cuda", aos=None, stream=None, sort_records: bool = False, merged: bool = False,
+                 record_ptrs=None):
         import torch
         self.torch = torch
-        self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
+        self.ptrs = record_ptrs
+        if record_ptrs is not None:
+            self.n = record_ptrs.numel()
+        else:
+            self.n = rec.shape[0] if rec is not None else aos.numel() // inputs.STRIDE
         self.p = params
         self.precision = precision
         self.merged = merged
@@ -522,13 +536,16 @@ class Stepper:
         if aos is None:
             aos = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(rec))).to(device)
         self.aos = aos
+        # what the calls take as the records: the buffer, or the address list
+        self.rec_arg = aos if record_ptrs is None else record_ptrs
+        fl = 0 if record_ptrs is None else DESC_RECORD_POINTERS
         u8 = dict(dtype=torch.uint8, device=device)
         self.state = torch.zeros(state_bytes(), **u8)
-        self.d_cells = cells_descriptor()
-        self.d_dens = density_descriptor()
-        self.d_force = force_descriptor()
-        self.d_kick = kick_descriptor()
-        self.d_merged = merged_descriptor()
+        self.d_cells = cells_descriptor(fl)
+        self.d_dens = density_descriptor(fl)
+        self.d_force = force_descriptor(fl)
+        self.d_kick = kick_descriptor(fl)
+        self.d_merged = merged_descriptor(fl)
         self.v_dens = self.v_force = self.cells = None
         self._make_cells()
         self.set_layouts(self.ld, self.lf)
@@ -547,7 +564,7 @@ class Stepper:
     # the pieces of a step, in order
     def build(self):
         begin_step(self.state, self.stream)
-        cells_build(self.cells, self.aos, self.d_cells, self.state, self.stream)
+        cells_build(self.cells, self.rec_arg, self.d_cells, self.state, self.stream)
         if self.sorting:
             self._sort_workspace()
             records_sort(self.cells, self.aos, inputs.STRIDE, self.sort_ws, self.stream)
@@ -571,7 +588,7 @@ class Stepper:
         soa_to_aos(self.v_force, self.stream)
 
     def kick(self):
-        kick_drift(self.aos, self.d_kick, self.n, self.p, self.state, self.stream)
+        kick_drift(self.rec_arg, self.d_kick, self.n, self.p, self.state, self.stream)
 
     def step(self):
         self.build()
@@ -592,7 +609,7 @@ class Stepper:
                 self.ld = self.lf = lay
                 self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_merged, self.n, lay,
                                                                               self.precision)), **u8)
-                self.v_dens = self.v_force = view_create(self.d_merged, self.n, lay, self.precision, self.aos,
+                self.v_dens = self.v_force = view_create(self.d_merged, self.n, lay, self.precision, self.rec_arg,
                                                          self.perm_ptr, self.ws_dens)
             if self.sorting:
                 self._sort_workspace()
@@ -604,7 +621,7 @@ class Stepper:
             self.ld = layout_density
             self.ws_dens = self.torch.empty(max(256, view_workspace_bytes(self.d_dens, self.n, self.ld,
                                                                           self.precision)), **u8)
-            self.v_dens = view_create(self.d_dens, self.n, self.ld, self.precision, self.aos, self.perm_ptr,
+            self.v_dens = view_create(self.d_dens, self.n, self.ld, self.precision, self.rec_arg, self.perm_ptr,
                                       self.ws_dens)
         if layout_force is not None:
             if self.v_force:
@@ -613,7 +630,7 @@ class Stepper:
             self.lf = layout_force
             self.ws_force = self.torch.empty(max(256, view_workspace_bytes(self.d_force, self.n, self.lf,
                                                                            self.precision)), **u8)
-            self.v_force = view_create(self.d_force, self.n, self.lf, self.precision, self.aos, self.perm_ptr,
+            self.v_force = view_create(self.d_force, self.n, self.lf, self.precision, self.rec_arg, self.perm_ptr,
                                        self.ws_force)
         if self.sorting:
             self._sort_workspace()      # allocated here, never inside a graph capture
@@ -696,6 +713,10 @@ class Stepper:
 
     def records(self) -> np.ndarray:
         self.torch.cuda.synchronize()
+        if self.ptrs is not None:
+            buf = self.aos.cpu().numpy()
+            slots = (self.ptrs.cpu().numpy().astype(np.int64) - self.aos.data_ptr()) // inputs.STRIDE
+            return buf.view(np.float64).reshape(-1, inputs.NSLOT)[slots].copy()
         return self.aos.cpu().numpy().view(np.float64).reshape(self.n, inputs.NSLOT).copy()
 
     def cells_arrays(self):

@@ -88,6 +88,50 @@ def test_descriptor_validation():
     assert _ws_bytes([("x", 0, sv.F64, sv.IN), ("y", 8 * n - 8, sv.F64, sv.IN)], n=n, stride=8) == 0
 
 
+def test_record_pointer_descriptors():
+    """Records reached through an address list: array-of-structs shape with an
+    8-byte multiple stride; unknown flag bits, other shapes and the sorted
+    layout are refused on the host; a list view plans the same storage as a
+    view of contiguous records and reports its members like one."""
+    fields = [("x", 0, sv.F64, sv.IN), ("h", 104, sv.F64, sv.INOUT)]
+    n = 100
+    plain = sv.view_workspace_bytes(sv.descriptor(fields), n, sv.layout(), sv.PREC_FP64)
+    listed = sv.view_workspace_bytes(sv.descriptor(fields, flags=sv.DESC_RECORD_POINTERS), n, sv.layout(),
+                                     sv.PREC_FP64)
+    assert plain == listed > 0
+    assert sv.view_workspace_bytes(sv.descriptor(fields, flags=2), n, sv.layout(), sv.PREC_FP64) == 0
+    assert sv.view_workspace_bytes(sv.descriptor(fields, stride=252, flags=sv.DESC_RECORD_POINTERS), n,
+                                   sv.layout(), sv.PREC_FP64) == 0
+    soa = [("x", 0, sv.F64, sv.IN), ("y", 8 * n, sv.F64, sv.IN)]
+    assert sv.view_workspace_bytes(sv.descriptor(soa, stride=8), n, sv.layout(), sv.PREC_FP64) > 0
+    assert sv.view_workspace_bytes(sv.descriptor(soa, stride=8, flags=sv.DESC_RECORD_POINTERS), n, sv.layout(),
+                                   sv.PREC_FP64) == 0
+    d = sv.density_descriptor(sv.DESC_RECORD_POINTERS)
+    fake = 1 << 40
+    sorted_l = sv.layout(sv.LAYOUT_SORTED)
+    with pytest.raises(sv.SphvError) as e:
+        sv.view_create(d, 10, sorted_l, sv.PREC_FP64, fake, None, fake,
+                       max(256, sv.view_workspace_bytes(d, 10, sorted_l, sv.PREC_FP64)))
+    assert e.value.status == sv.E_UNSUPPORTED
+    for bad in (2, 1 << 31):
+        with pytest.raises(sv.SphvError) as e:
+            sv.view_create(sv.density_descriptor(bad), 10, sv.layout(), sv.PREC_FP64, fake, None, fake, 1 << 20)
+        assert e.value.status == sv.E_DESCRIPTOR
+    v = sv.view_create(d, 10, sv.layout(), sv.PREC_FP64, fake, None, fake, sv.view_workspace_bytes(d, 10,
+                                                                                               sv.layout(),
+                                                                                               sv.PREC_FP64))
+    ptr, dt, bl, bb = sv.view_field(v, 0)
+    assert ptr == fake and dt == sv.F64 and bl == 10
+    sv.view_destroy(v)
+    # the tuners take contiguous records only
+    p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
+    cells = sv.cells_create(10, p, fake, sv.cells_workspace_bytes(10, p))
+    with pytest.raises(sv.SphvError) as e:
+        sv.autotune(0, fake, d, cells, p, sv.PREC_FP64, fake, ws_bytes=1 << 30)
+    assert e.value.status == sv.E_UNSUPPORTED
+    sv.cells_destroy(cells)
+
+
 def test_workspace_sizes():
     d = sv.density_descriptor()
     a = sv.view_workspace_bytes(d, 1000, sv.layout(), sv.PREC_FP64)
