@@ -368,6 +368,22 @@ int32_t sphv_view_create(sphv_view** out, const sphv_descriptor* d, int64_t n,
  * (which copy nothing but write the records' members in place) open and
  * take part in this rule like the others. */
 int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream);
+/* Prefetch: gathers ahead the members of A_in that the view only reads and
+ * that no open (or prefetched) view on the same records writes, so that the
+ * copy can overlap other work, e.g. the force view's positions, velocities,
+ * masses, u and alpha on a second stream while the density loop runs (the
+ * paper's Sec. 7.5 on overlapping transfers with kernels; with records in
+ * pinned host memory this hides their transfer).  The view is then registered
+ * as a reader of those members: a view that writes one of them fails to open
+ * with SPHV_E_ALIAS, and the caller must not change them in the records before
+ * the view closes.  sphv_aos_to_soa later gathers the remaining members and
+ * opens the view; only the prefetched members' bits are taken at prefetch
+ * time.  A view on the records themselves copies nothing (SPHV_OK, no
+ * effect); so does a view none of whose members qualify.  SPHV_E_STATE if the
+ * view is open or prefetched already, or cells are missing for an FP32 view.
+ * Ordering between the two streams is the caller's: the prefetch must follow
+ * cells_build (the view's index), and the loop must follow the prefetch. */
+int32_t sphv_aos_to_soa_prefetch(sphv_view* v, const sphv_cells* cells, void* stream);
 /* Scatter A_out only (the epilogue) and close the view. */
 int32_t sphv_soa_to_aos(sphv_view* v, void* stream);
 /* Device address, dtype and element stride (bytes between consecutive elements

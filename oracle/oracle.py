@@ -165,10 +165,52 @@ def bin_keys(x, y, z, lo, inv_cell, grid):
     return np.where(bad, 0, key)
 
 
-def sort_cells(keys, ncell):
-    """Stable sort by key (ties keep the original index order), cell offsets."""
-    perm = np.argsort(keys, kind="stable").astype(np.int64)
+# Second level of the cells (a refinement of dense cells, as the paper's
+# spacetree refines cells that hold many particles, Sec. 2.1): each cell is
+# split into SUB^3 sub-cells, and inside a cell of more than DENSE particles
+# the particles are ordered by the Morton (bit-interleaved) index of their
+# sub-cell, so that consecutive runs of them are compact in space.
+SUB_BITS = 4
+DENSE = 64
+
+
+def sub_keys(x, y, z, lo, inv_cell, grid):
+    """Morton index of a particle's sub-cell inside its cell: along each axis
+    t = (x - lo) * inv_cell (each step rounded, as for the key), k the cell
+    index bin_keys takes (t floored and clamped to the grid), s =
+    clamp(floor((t - k) * 2^SUB_BITS), 0, 2^SUB_BITS - 1); bit b of s_x, s_y,
+    s_z goes to bit 3b, 3b+1, 3b+2 of the index.  Non-finite coordinates give 0."""
+    n_sub = 1 << SUB_BITS
+    s = []
+    for v, l, ic, n in zip((x, y, z), lo, inv_cell, grid):
+        t = (np.asarray(v, dtype=np.float64) - np.float64(l)) * np.float64(ic)
+        ok = np.isfinite(t)
+        t = np.where(ok, t, 0.0)
+        k = np.clip(np.floor(t), 0, n - 1)
+        q = np.floor((t - k) * np.float64(n_sub))
+        s.append(np.clip(q, 0, n_sub - 1).astype(np.int64))
+    code = np.zeros_like(s[0])
+    for b in range(SUB_BITS):
+        for d in range(3):
+            code |= ((s[d] >> b) & 1) << (3 * b + d)
+    bad = ~(np.isfinite(x) & np.isfinite(y) & np.isfinite(z))
+    return np.where(bad, 0, code)
+
+
+def sort_cells(keys, ncell, sub=None):
+    """Order of the particles by cell, cell offsets.  Within a cell, particles
+    keep their original index order (the stable sort by key); with sub given,
+    inside cells of more than DENSE particles they are ordered by sub-cell
+    index first, ties by original index."""
+    keys = np.asarray(keys, dtype=np.int64)
     counts = np.bincount(keys, minlength=ncell)
+    if sub is None:
+        perm = np.argsort(keys, kind="stable").astype(np.int64)
+    else:
+        dense = counts[keys] > DENSE
+        second = np.where(dense, np.asarray(sub, dtype=np.int64), 0)
+        idx = np.arange(keys.shape[0], dtype=np.int64)
+        perm = np.lexsort((idx, second, keys)).astype(np.int64)
     start = np.zeros(ncell + 1, dtype=np.int64)
     np.cumsum(counts, out=start[1:])
     return perm, start

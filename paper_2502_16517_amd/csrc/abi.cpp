@@ -163,8 +163,9 @@ struct sphv_view {
     uint64_t block_bytes = 0;
     uint32_t lw = 63;
     double* red_part = nullptr; // reduction partials
-    int open = 0;               // 1 between aos_to_soa and soa_to_aos
+    int open = 0;               // 1 between aos_to_soa and soa_to_aos; 2 after a prefetch
     int gathered = 0;
+    uint64_t prefetched = 0;    // bit k: member k of the plan was gathered by a prefetch
 };
 
 struct sphv_graph {
@@ -177,13 +178,23 @@ namespace {
 std::mutex g_open_mutex;
 std::vector<sphv_view*> g_open;
 
+// How view v uses member k while registered: as described when open, read
+// only and only the prefetched members after a prefetch.
+uint16_t member_use(const sphv_view* v, size_t k)
+{
+    if (v->open == 2) return ((v->prefetched >> k) & 1u) ? (uint16_t)SPHV_IN : (uint16_t)0;
+    return v->plan[k].f.access;
+}
+
 bool members_meet(const sphv_view* a, uint16_t amask, const sphv_view* b, uint16_t bmask)
 {
-    for (const FieldPlan& x : a->plan) {
-        if (!(x.f.access & amask)) continue;
+    for (size_t i = 0; i < a->plan.size(); ++i) {
+        const FieldPlan& x = a->plan[i];
+        if (!(member_use(a, i) & amask)) continue;
         uint64_t x0 = x.f.offset, x1 = x0 + dtype_size(x.f.dtype);
-        for (const FieldPlan& y : b->plan) {
-            if (!(y.f.access & bmask)) continue;
+        for (size_t k = 0; k < b->plan.size(); ++k) {
+            const FieldPlan& y = b->plan[k];
+            if (!(member_use(b, k) & bmask)) continue;
             uint64_t y0 = y.f.offset, y1 = y0 + dtype_size(y.f.dtype);
             if (x0 < y1 && y0 < x1) return true;
         }
@@ -262,6 +273,7 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t lis
     int64_t max_items = std::min<int64_t>(nc, n) + (n + kWave - 1) / kWave + 1;
     int64_t scan_blocks = (std::max(nc, max_items) + 1023) / 1024 + 1;
     c->key = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
+    c->sub = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
     c->perm = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
     c->perm_tmp = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
     c->key_sorted = (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1));
@@ -284,6 +296,7 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t lis
     c->list_cap = list_cap;
     c->list = list_cap > 0 ? (int32_t*)take(4 * (uint64_t)list_cap * (uint64_t)std::max<int64_t>(n, 1)) : nullptr;
     c->fconst = (double*)take(5 * 8 * (uint64_t)std::max<int64_t>(n, 1));
+    c->blocks = list_cap > 0 ? (double*)take(8ull * kBlockWords * (uint64_t)(n / kBlock + 1)) : nullptr;
     c->n = n;
     c->nc = nc;
     c->max_items = max_items;
@@ -673,35 +686,17 @@ int32_t sphv_view_field(const sphv_view* v, uint32_t k, void** ptr, int32_t* dty
     return SPHV_OK;
 }
 
-int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
+namespace {
+
+// Gathers the plan members of v selected by mask (records -> view storage).
+int32_t gather_members(sphv_view* v, const sphv_cells* cells, bool needs_cells, uint64_t mask, void* stream)
 {
-    if (!v) return SPHV_E_INVALID_ARG;
-    if (v->open) return SPHV_E_STATE;
-    bool needs_cells = false;
-    for (const FieldPlan& p : v->plan) needs_cells |= p.rel_axis >= 0;
-    if (needs_cells && (!cells || !cells->built || cells->dev.n != v->n || v->index != cells->dev.perm))
-        return SPHV_E_STATE;
-    // the gather reads the records: checked once per view, before its first
-    // gather (a view on the records is checked by the first loop call instead)
-    if (!is_direct(v->layout.kind))
-        if (int32_t r = records_ok(v)) return r;
-    {
-        // views on the records themselves (direct, sorted) write the records'
-        // members in place, so they take part in the rule like any other view
-        std::lock_guard<std::mutex> lk(g_open_mutex);
-        for (sphv_view* o : g_open)
-            if (views_conflict(v, o)) return SPHV_E_ALIAS;
-        g_open.push_back(v);
-    }
-    v->open = 1;
-    v->gathered = 1;
-    if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;
     FieldRef src[kMaxFields], dst[kMaxFields];
     int nf = 0;
-    for (const FieldPlan& p : v->plan) {
-        if (!(p.f.access & SPHV_IN)) continue;     // A_out \ A_in needs no preparation
-        src[nf] = ref_rec(v->aos, p.f, v->desc);
-        dst[nf] = ref_view(v, p);
+    for (size_t k = 0; k < v->plan.size(); ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        src[nf] = ref_rec(v->aos, v->plan[k].f, v->desc);
+        dst[nf] = ref_view(v, v->plan[k]);
         ++nf;
     }
     if (!nf) return SPHV_OK;
@@ -716,15 +711,85 @@ int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
     return hip_status(launch_gather(src, dst, nf, sa, da, key, g, v->n, (hipStream_t)stream));
 }
 
+bool cells_fit(const sphv_view* v, const sphv_cells* cells, bool& needs_cells)
+{
+    needs_cells = false;
+    for (const FieldPlan& p : v->plan) needs_cells |= p.rel_axis >= 0;
+    return !(needs_cells && (!cells || !cells->built || cells->dev.n != v->n || v->index != cells->dev.perm));
+}
+
+}  // namespace
+
+int32_t sphv_aos_to_soa_prefetch(sphv_view* v, const sphv_cells* cells, void* stream)
+{
+    if (!v) return SPHV_E_INVALID_ARG;
+    if (v->open) return SPHV_E_STATE;
+    bool needs_cells = false;
+    if (!cells_fit(v, cells, needs_cells)) return SPHV_E_STATE;
+    if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;     // nothing is copied
+    if (int32_t r = records_ok(v)) return r;
+    uint64_t mask = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_open_mutex);
+        // the members v only reads and that no registered view writes
+        for (size_t k = 0; k < v->plan.size(); ++k) {
+            if (v->plan[k].f.access != SPHV_IN) continue;
+            v->prefetched = 1ull << k;
+            v->open = 2;
+            bool free = true;
+            for (sphv_view* o : g_open) free = free && !views_conflict(v, o);
+            if (free) mask |= 1ull << k;
+        }
+        v->prefetched = mask;
+        v->open = mask ? 2 : 0;
+        if (mask) g_open.push_back(v);
+    }
+    return gather_members(v, cells, needs_cells, mask, stream);
+}
+
+int32_t sphv_aos_to_soa(sphv_view* v, const sphv_cells* cells, void* stream)
+{
+    if (!v) return SPHV_E_INVALID_ARG;
+    if (v->open == 1) return SPHV_E_STATE;
+    bool needs_cells = false;
+    if (!cells_fit(v, cells, needs_cells)) return SPHV_E_STATE;
+    // the gather reads the records: checked once per view, before its first
+    // gather (a view on the records is checked by the first loop call instead)
+    if (!is_direct(v->layout.kind))
+        if (int32_t r = records_ok(v)) return r;
+    {
+        // views on the records themselves (direct, sorted) write the records'
+        // members in place, so they take part in the rule like any other view;
+        // after a prefetch the view is registered already, as a reader of the
+        // members it prefetched, and now takes all of its members
+        std::lock_guard<std::mutex> lk(g_open_mutex);
+        const int was = v->open;
+        v->open = 1;
+        for (sphv_view* o : g_open)
+            if (o != v && views_conflict(v, o)) {
+                v->open = was;
+                return SPHV_E_ALIAS;
+            }
+        if (!was) g_open.push_back(v);
+    }
+    v->gathered = 1;
+    if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;
+    uint64_t mask = 0;
+    for (size_t k = 0; k < v->plan.size(); ++k)
+        if ((v->plan[k].f.access & SPHV_IN) && !((v->prefetched >> k) & 1u)) mask |= 1ull << k;  // A_out \ A_in: none
+    return gather_members(v, cells, needs_cells, mask, stream);
+}
+
 int32_t sphv_soa_to_aos(sphv_view* v, void* stream)
 {
     if (!v) return SPHV_E_INVALID_ARG;
-    if (!v->open) return SPHV_E_STATE;
+    if (v->open != 1) return SPHV_E_STATE;
     {
         std::lock_guard<std::mutex> lk(g_open_mutex);
         g_open.erase(std::remove(g_open.begin(), g_open.end(), v), g_open.end());
     }
     v->open = 0;
+    v->prefetched = 0;
     if (is_direct(v->layout.kind) || v->n == 0) return SPHV_OK;
     FieldRef src[kMaxFields], dst[kMaxFields];
     int nf = 0;
@@ -761,7 +826,7 @@ int32_t pair_setup(sphv_view* v, const sphv_cells* c, const sphv_params* p, void
 {
     if (!v || !c || !p || !state) return SPHV_E_INVALID_ARG;
     if (!finite_params(p)) return SPHV_E_INVALID_ARG;
-    if (!v->open) return SPHV_E_STATE;
+    if (v->open != 1) return SPHV_E_STATE;
     if (!c->built || c->dev.n != v->n || v->index != c->dev.perm) return SPHV_E_STATE;
     for (int k = 0; k < nin; ++k) if (int32_t s = need(v, roles_in[k], SPHV_IN)) return s;
     for (int k = 0; k < nout; ++k) if (int32_t s = need(v, roles_out[k], SPHV_OUT)) return s;
@@ -828,8 +893,11 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     if (c->dev.list_cap > 0) {
         a.list = c->dev.list;
         a.list_cap = c->dev.list_cap;
-        return hip_status(launch_density_list(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
-                                              p->kernel, (hipStream_t)stream));
+        const int direct = is_direct(v->layout.kind), fp32 = v->precision == SPHV_PREC_FP32;
+        if (launch_block_bounds(a, c->dev.blocks, direct, fp32, (hipStream_t)stream) != hipSuccess)
+            return SPHV_E_HIP;
+        a.blocks = c->dev.blocks;
+        return hip_status(launch_density_list(a, direct, fp32, p->kernel, (hipStream_t)stream));
     }
     return hip_status(launch_density(a, is_direct(v->layout.kind), v->precision == SPHV_PREC_FP32,
                                      (int)v->layout.masked, p->kernel, (hipStream_t)stream));
@@ -870,6 +938,10 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     if (c->dev.list_cap > 0) {
         a.list = c->dev.list;
         a.list_cap = c->dev.list_cap;
+        if (launch_block_bounds(a, c->dev.blocks, direct, v->precision == SPHV_PREC_FP32, st) != hipSuccess)
+            return SPHV_E_HIP;
+        a.blocks = c->dev.blocks;
+        a.cell_h = c->dev.hmax_f;
         return hip_status(launch_force_list(a, direct, v->precision == SPHV_PREC_FP32, p->kernel, st));
     }
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, p->kernel, st));
@@ -879,7 +951,7 @@ int32_t sphv_step_reduce(sphv_view* v, const sphv_params* p, void* state, void* 
 {
     if (!v || !p || !state) return SPHV_E_INVALID_ARG;
     if (!finite_params(p)) return SPHV_E_INVALID_ARG;
-    if (!v->open) return SPHV_E_STATE;
+    if (v->open != 1) return SPHV_E_STATE;
     const int rin[6] = {SPHV_M, SPHV_VX, SPHV_VY, SPHV_VZ, SPHV_U, SPHV_H};
     const int rout[5] = {SPHV_AX, SPHV_AY, SPHV_AZ, SPHV_UDT, SPHV_VSIG};
     for (int k = 0; k < 6; ++k) if (int32_t s = need(v, rin[k], SPHV_IN)) return s;

@@ -18,6 +18,10 @@ constexpr int kQStride = 1024;   // ints between two queue heads: one 4 KiB page
                                  // atomics do not queue up at one memory channel
 constexpr int kMaxPairBlocks = 256 * 20;   // largest grid of a pair loop
 constexpr int kPartSlots = 4;    // per-wave counters a pair loop leaves for its fold
+constexpr int kDense = 64;       // cells of more particles are ordered by sub-cell inside
+constexpr int kSubBits = 4;      // sub-cells per cell edge: 2^kSubBits
+constexpr int kBlock = 64;       // sorted positions per bounding block of the list walks
+constexpr int kBlockWords = 8;   // per block: lo x y z, hi x y z, largest 2h, spare
 
 // Device state block (mirrors sphv_state field for field).
 struct DevState {
@@ -68,6 +72,7 @@ struct Geom {
 
 struct CellsDev {
     int32_t* key;          // [n] key of record i
+    int32_t* sub;          // [n] sub-cell code of record i (Morton index of its 16^3 sub-cell)
     int32_t* perm;         // [n]
     int32_t* perm_tmp;     // [n] cell-grouped, not yet ordered within a cell
     int32_t* key_sorted;   // [n] cell of sorted position p
@@ -90,6 +95,7 @@ struct CellsDev {
     int32_t* meta;         // [META_SIZE]: item count, mask tag, force R_global, queue heads
     int32_t* list;         // [list_cap][n] neighbour lists (list walks only, else null)
     double* fconst;        // [5][n] per-particle force constants (of the pair precision)
+    double* blocks;        // [n / 64 + 1][kBlockWords] bounds of each run of 64 sorted positions (list walks)
     int32_t list_cap;
     int32_t pad_l;
     int64_t n;
@@ -134,6 +140,8 @@ struct PairArgs {
     double cfl;
     int32_t* list;             // list walks: entry k of sorted position p at list[k n + p]
     void* fconst;              // force: per-particle constants (R[5][n], R the pair precision)
+    const double* blocks;      // list walks: bounds of each run of kBlock sorted positions, or null
+    const uint32_t* cell_h;    // force list walk: float bits of each cell's largest 2h (rounded up)
     int32_t list_cap;
     int32_t pad3;
 };
@@ -162,6 +170,8 @@ hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kern
 hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kernel, hipStream_t s);
 // per-particle constants of both force loops (k_list.hip), into a.fconst
 hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_t s);
+// bounds of each run of kBlock sorted positions into blocks (k_list.hip)
+hipError_t launch_block_bounds(const PairArgs& a, double* blocks, int direct, int fp32, hipStream_t s);
 hipError_t launch_pair_fold(const PairArgs& a, int nblocks, int density, hipStream_t s);
 // in_view: in6 are members of the view (read with outacc) instead of the records
 hipError_t launch_force_reduce(const FieldRef* in6, const Access& rec, const FieldRef* out5,

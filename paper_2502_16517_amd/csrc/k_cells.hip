@@ -72,20 +72,31 @@ __global__ void k_state_init(DevState* st, int full)
 // Cell key and support bits of one particle; flags non-finite input and
 // particles outside an open box.
 __device__ __forceinline__ void bin_one(const double c[3], double h, const Geom& g, DevState* st, int& kk,
-                                        uint32_t& hbits)
+                                        uint32_t& hbits, int& sub)
 {
     bool finite = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]);
     int k[3];
+    int s[3];
     bool outside = false;
     for (int d = 0; d < 3; ++d) {
         // k_d = clamp(floor((x_d - lo_d) * inv_cell_d), 0, n_d - 1), each step rounded
-        double t = floor(__dmul_rn(__dsub_rn(c[d], g.lo[d]), g.inv_cell[d]));
-        if (!isfinite(t)) t = 0.0;
+        double tr = __dmul_rn(__dsub_rn(c[d], g.lo[d]), g.inv_cell[d]);
+        if (!isfinite(tr)) tr = 0.0;
+        double t = floor(tr);
         if (t < 0.0) { t = 0.0; outside = true; }
         if (t > (double)(g.n[d] - 1)) { t = (double)(g.n[d] - 1); outside = true; }
         k[d] = (int)t;
+        // sub-cell inside the cell: floor((t_raw - k) 2^kSubBits), clamped
+        double q = floor(__dmul_rn(__dsub_rn(tr, t), (double)(1 << kSubBits)));
+        q = q < 0.0 ? 0.0 : (q > (double)((1 << kSubBits) - 1) ? (double)((1 << kSubBits) - 1) : q);
+        s[d] = (int)q;
     }
     kk = finite ? cell_key(k[0], k[1], k[2], g) : 0;
+    // Morton index: bit b of s_x, s_y, s_z at bits 3b, 3b + 1, 3b + 2
+    sub = 0;
+    for (int b = 0; b < kSubBits; ++b)
+        for (int d = 0; d < 3; ++d) sub |= ((s[d] >> b) & 1) << (3 * b + d);
+    if (!finite) sub = 0;
     // support radius with headroom; positive floats order like their bits
     float H = __double2float_ru(2.0 * h * g.headroom);
     if (!(isfinite(h) && h > 0.0)) {
@@ -106,8 +117,8 @@ __device__ __forceinline__ void bin_one(const double c[3], double h, const Geom&
 }
 
 __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, const FieldRef fh,
-                      uint64_t stride, const uint64_t* ptrs, Geom g, int64_t n, int32_t* key, int32_t* counts,
-                      uint32_t* hmax_bits, DevState* st)
+                      uint64_t stride, const uint64_t* ptrs, Geom g, int64_t n, int32_t* key, int32_t* sub,
+                      int32_t* counts, uint32_t* hmax_bits, DevState* st)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -118,10 +129,11 @@ __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, c
     c[1] = *at(fy);
     c[2] = *at(fz);
     const double h = *at(fh);
-    int kk;
+    int kk, sb;
     uint32_t hb;
-    bin_one(c, h, g, st, kk, hb);
+    bin_one(c, h, g, st, kk, hb, sb);
     key[i] = kk;
+    sub[i] = sb;
     atomicAdd(&counts[kk], 1);
     atomicMax(&hmax_bits[kk], hb);
 }
@@ -130,8 +142,8 @@ __global__ void k_bin(const FieldRef fx, const FieldRef fy, const FieldRef fz, c
 // lattice row, say) add to their cell's counters once per run of lanes.
 __global__ __launch_bounds__(kStageThreads) void k_bin_staged(const FieldRef fx, const FieldRef fy, const FieldRef fz,
                                                               const FieldRef fh, StagePlan sp, uint64_t stride,
-                                                              Geom g, int64_t n, int32_t* key, int32_t* counts,
-                                                              uint32_t* hmax_bits, DevState* st)
+                                                              Geom g, int64_t n, int32_t* key, int32_t* sub,
+                                                              int32_t* counts, uint32_t* hmax_bits, DevState* st)
 {
     extern __shared__ uint4 tile[];
     const int64_t r0 = (int64_t)blockIdx.x * kStageThreads;
@@ -143,8 +155,10 @@ __global__ __launch_bounds__(kStageThreads) void k_bin_staged(const FieldRef fx,
     if (valid) {
         const LocTile l{(char*)&tile[threadIdx.x * sp.nch] - (uint64_t)sp.c0 * 16};
         const double c[3] = {*(const double*)l.at(fx), *(const double*)l.at(fy), *(const double*)l.at(fz)};
-        bin_one(c, *(const double*)l.at(fh), g, st, kk, hb);
+        int sb;
+        bin_one(c, *(const double*)l.at(fh), g, st, kk, hb, sb);
         key[i] = kk;
+        sub[i] = sb;
     }
     const int head = run_head(kk, valid);
     hb = run_max_upto(hb, head);
@@ -271,14 +285,17 @@ constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
 
 // One wave per pair of cells (grid-stride): order each cell's record indices
 // ascending, which, since the indices are distinct, is the stable order of the
-// sort.  Two cells of at most 32 particles are sorted side by side, one per
-// half-wave; otherwise the cells are sorted one after the other.
+// sort; inside a cell of more than kDense particles the order is by sub-cell
+// code first (the second level of the cells), then by index.  Two cells of at
+// most 32 particles are sorted side by side, one per half-wave; otherwise the
+// cells are sorted one after the other.
 __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_start, const int32_t* perm_tmp,
-                                                          int32_t* perm, int32_t* key_sorted,
+                                                          const int32_t* sub, int32_t* perm, int32_t* key_sorted,
                                                           const uint32_t* hmax_bits, int32_t* reach_d,
                                                           Geom g, int64_t nc)
 {
     __shared__ int lds[kSortWaves][kSortLds];
+    __shared__ uint16_t lsub[kSortWaves][kSortLds];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     int* buf = lds[w];
@@ -306,13 +323,23 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
                 key_sorted[b + lane] = (int32_t)c;
             }
         } else if (cnt <= kSortLds) {
-            for (int k = lane; k < cnt; k += kWave) buf[k] = perm_tmp[b + k];
+            // a dense cell: rank by (sub-cell code, index)
+            uint16_t* bsub = lsub[w];
+            for (int k = lane; k < cnt; k += kWave) {
+                const int v = perm_tmp[b + k];
+                buf[k] = v;
+                bsub[k] = (uint16_t)sub[v];
+            }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_s_waitcnt(0);
             for (int k = lane; k < cnt; k += kWave) {
-                int v = buf[k];
+                const int v = buf[k];
+                const int sv = bsub[k];
                 int rank = 0;
-                for (int t = 0; t < cnt; ++t) rank += buf[t] < v;
+                for (int t = 0; t < cnt; ++t) {
+                    const int st = bsub[t];
+                    rank += (st < sv || (st == sv && buf[t] < v)) ? 1 : 0;
+                }
                 perm[b + rank] = v;
                 key_sorted[b + k] = (int32_t)c;
             }
@@ -320,9 +347,14 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
             __builtin_amdgcn_s_waitcnt(0);
         } else {
             for (int k = lane; k < cnt; k += kWave) {
-                int v = perm_tmp[b + k];
+                const int v = perm_tmp[b + k];
+                const int sv = sub[v];
                 int rank = 0;
-                for (int t = 0; t < cnt; ++t) rank += perm_tmp[b + t] < v;
+                for (int t = 0; t < cnt; ++t) {
+                    const int u = perm_tmp[b + t];
+                    const int su = sub[u];
+                    rank += (su < sv || (su == sv && u < v)) ? 1 : 0;
+                }
                 perm[b + rank] = v;
                 key_sorted[b + k] = (int32_t)c;
             }
@@ -734,11 +766,10 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
         if (!rec.index && !rec.ptrs && plan_stage(f, 4, 0u, rec.stride, &sp))
             hipLaunchKernelGGL(k_bin_staged, dim3(nblk(c.n, kStageThreads)), dim3(kStageThreads),
                                kStageThreads * sp.nch * 16, s, f[0], f[1], f[2], f[3], sp, rec.stride, g, c.n, c.key,
-                               c.counts, c.hmax_bits, st);
+                               c.sub, c.counts, c.hmax_bits, st);
         else
             hipLaunchKernelGGL(k_bin, dim3(nblk(c.n, 256)), dim3(256), 0, s, f[0], f[1], f[2], f[3], rec.stride,
-                               rec.ptrs, g,
-                               c.n, c.key, c.counts, c.hmax_bits, st);
+                               rec.ptrs, g, c.n, c.key, c.sub, c.counts, c.hmax_bits, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan_excl(c.counts, c.nc, c.scan_part, c.cell_start, c.cursor, c.meta + META_SCAN, s)) != hipSuccess)
@@ -748,7 +779,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     unsigned sb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((c.nc + 1) / 2 + kSortWaves - 1) / kSortWaves, 8192));
-    hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.perm,
+    hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.sub, c.perm,
                        c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nrows = (int64_t)g.n[1] * g.n[2];

@@ -236,13 +236,81 @@ __device__ __forceinline__ R diff(const PairArgs& a, R xi, R yi, R zi, const P& 
     return dx * dx + dy * dy + dz * dz;
 }
 
+// Bounds of each run of kBlock sorted positions (the last run may be
+// shorter): the lower and upper corner of its particles' positions in the box
+// frame (FP64; an FP32 view's cell-relative coordinates are moved back by
+// their cell's corner and the box widened by their rounding) and its largest
+// 2h.  A dense cell (more than kDense particles, ordered by sub-cell) holds
+// compact runs, so the window walks skip runs that lie out of reach.
+template <bool DIRECT, bool FP32>
+__global__ __launch_bounds__(kWave) void k_block_bounds(PairArgs a, double* out)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = p < a.n;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, H = 0.0;
+    if (valid) {
+        const Loc<DIRECT> l = locate<DIRECT>(a.acc, p);
+        double x[3];
+        if constexpr (FP32) {
+            int k[3];
+            cell_coords(a.key_sorted[p], a.g, k[0], k[1], k[2]);
+            const int roles[3] = {SPHV_X, SPHV_Y, SPHV_Z};
+            for (int d = 0; d < 3; ++d) {
+                const double o = __dadd_rn(a.g.lo[d], __dmul_rn((double)k[d], a.g.cell[d]));
+                const double v = (double)ld_rel(a.f[roles[d]], l, a.g, d, k[d]) + o;
+                const double e = a.g.cell[d] * 0x1p-20;      // far above the float rounding of the offset
+                lo[d] = v - e;
+                hi[d] = v + e;
+            }
+        } else {
+            x[0] = ld_f64(a.f[SPHV_X], l);
+            x[1] = ld_f64(a.f[SPHV_Y], l);
+            x[2] = ld_f64(a.f[SPHV_Z], l);
+            for (int d = 0; d < 3; ++d) lo[d] = hi[d] = x[d];
+        }
+        H = 2.0 * (FP32 ? (double)ld_f32v(a.f[SPHV_H], l) : ld_f64(a.f[SPHV_H], l));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, kWave));
+            hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, kWave));
+        }
+        H = fmax(H, __shfl_xor(H, off, kWave));
+    }
+    if (threadIdx.x == 0) {
+        double* o = out + (int64_t)blockIdx.x * kBlockWords;
+        for (int d = 0; d < 3; ++d) {
+            o[d] = lo[d];
+            o[3 + d] = hi[d];
+        }
+        o[6] = H;
+        o[7] = 0.0;
+    }
+}
+
+// Distance from coordinate p to the slab of cell index k (not wrapped: the
+// window's own image) along axis d.
+__device__ __forceinline__ double slab_dist(double p, int k, const Geom& g, int d)
+{
+    const double lo = g.lo[d] + (double)k * g.cell[d];
+    return fmax(fmax(lo - p, p - (lo + g.cell[d])), 0.0);
+}
+
 // Walks the window of cell (kx, ky, kz) with per-axis reach r in a fixed order
 // (dz, dy, then the row's cells along x: wrapped left part, main part, wrapped
 // right part) and calls visit(j, jx, jy, jz, ox, oy, oz) for every candidate j
 // (sorted position) of cell (jx, jy, jz), (ox, oy, oz) being that cell's
-// offset from the local cell in the window.
-template <class V>
-__device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], V&& visit)
+// offset from the local cell in the window.  Candidates that cannot be within
+// reach of the local particle at (px, py, pz) (box frame) are skipped, in the
+// same way for every walk of that particle: a row of cells whose (y, z)
+// distance d2 fails keep_cell(d2, -1), a cell whose box distance fails
+// keep_cell(d2, key), and, in a cell of more than kDense particles with block
+// bounds given, a run of kBlock sorted positions whose bounds fail
+// keep_block(bounds, sx, sy, sz), (sx, sy, sz) being the periodic shift of the
+// cell's image.
+template <class KC, class KB, class V>
+__device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], double px,
+                                            double py, double pz, KC&& keep_cell, KB&& keep_block, V&& visit)
 {
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
     for (int dz = -r[2]; dz <= r[2]; ++dz) {
@@ -251,12 +319,16 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
             if (!a.g.periodic[2]) continue;
             z2 += z2 < 0 ? nz : -nz;
         }
+        const double ez = slab_dist(pz, kz + dz, a.g, 2);
         for (int dy = -r[1]; dy <= r[1]; ++dy) {
             int y2 = ky + dy;
             if (y2 < 0 || y2 >= ny) {
                 if (!a.g.periodic[1]) continue;
                 y2 += y2 < 0 ? ny : -ny;
             }
+            const double ey = slab_dist(py, ky + dy, a.g, 1);
+            const double dyz = fma(ey, ey, ez * ez);
+            if (!keep_cell(dyz, -1)) continue;
             const int row = (z2 * ny + y2) * nx;
             for (int dx = -r[0]; dx <= r[0]; ++dx) {
                 int x2 = kx + dx;
@@ -264,12 +336,49 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
                     if (!a.g.periodic[0]) continue;
                     x2 += x2 < 0 ? nx : -nx;
                 }
+                const double ex = slab_dist(px, kx + dx, a.g, 0);
+                if (!keep_cell(fma(ex, ex, dyz), row + x2)) continue;
                 const int jb = a.cell_start[row + x2];
                 const int je = a.cell_start[row + x2 + 1];
-                for (int j = jb; j < je; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+                if (a.blocks && je - jb > kDense) {
+                    const double sx = kx + dx - x2 > 0 ? a.g.len[0] : (kx + dx - x2 < 0 ? -a.g.len[0] : 0.0);
+                    const double sy = ky + dy - y2 > 0 ? a.g.len[1] : (ky + dy - y2 < 0 ? -a.g.len[1] : 0.0);
+                    const double sz = kz + dz - z2 > 0 ? a.g.len[2] : (kz + dz - z2 < 0 ? -a.g.len[2] : 0.0);
+                    for (int b0 = jb; b0 < je;) {
+                        const int bk = b0 / kBlock;
+                        const int b1 = (bk + 1) * kBlock < je ? (bk + 1) * kBlock : je;
+                        if (keep_block(a.blocks + (int64_t)bk * kBlockWords, sx, sy, sz))
+                            for (int j = b0; j < b1; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+                        b0 = b1;
+                    }
+                } else {
+                    for (int j = jb; j < je; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+                }
             }
         }
     }
+}
+
+// Squared distance from (px, py, pz) minus the shift to the box of a run's bounds.
+__device__ __forceinline__ double box_d2(const double* bnd, double px, double py, double pz, double sx, double sy,
+                                         double sz)
+{
+    const double p[3] = {px - sx, py - sy, pz - sz};
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = fmax(fmax(bnd[d] - p[d], p[d] - bnd[3 + d]), 0.0);
+        d2 = fma(e, e, d2);
+    }
+    return d2;
+}
+
+// The local particle's position in the box frame, FP64: as stored, or an FP32
+// view's cell-relative coordinate moved back by its cell's corner.
+template <bool FP32, class R>
+__device__ __forceinline__ double box_pos(R v, const Geom& g, int d, int k)
+{
+    if constexpr (FP32) return (double)v + __dadd_rn(g.lo[d], __dmul_rn((double)k, g.cell[d]));
+    else return v;
 }
 
 // ================================================================ density
@@ -319,6 +428,19 @@ __global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
         const double h0 = ld_f64(a.f[SPHV_H], li);
         const double hl = fmin(hcap, kGrowL * h0);
         const R Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
+        // block culling: the runs within reach of the radius rc
+        const double bx = box_pos<FP32>(xi, a.g, 0, kx), by = box_pos<FP32>(yi, a.g, 1, ky),
+                     bz = box_pos<FP32>(zi, a.g, 2, kz);
+        double rc2 = 0.0;
+        auto keep = [&](const double* bnd, double sx, double sy, double sz) {
+            return box_d2(bnd, bx, by, bz, sx, sy, sz) < rc2;
+        };
+        auto keep_cell = [&](double d2, int) { return d2 < rc2; };
+        auto cull_radius = [&](double hh) {
+            const double rr = 2.0 * hh * (1.0 + 1e-6) + (FP32 ? a.g.cmin * 0x1p-18 : 0.0);
+            rc2 = rr * rr;
+        };
+        cull_radius(hl);
 
         // candidate j of the window, loaded and placed in the local frame
         auto cand = [&](int j, int jx, int jy, int jz, int ox, int oy, int oz, R& cm) {
@@ -333,7 +455,8 @@ __global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
         // ---- build: the candidates within the list radius, in window order
         int32_t* L = a.list + p;
         int len = 0;
-        walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox, int oy,
+                                                                        int oz) {
             Pos<DIRECT, FP32> c;
             const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
             if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
@@ -419,7 +542,9 @@ __global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
                 // stays within h_l, those are exactly the list's entries, in its
                 // order, so the FP32 partial sums are grouped as in the list walk)
                 // and every candidate in range at the current h
-                walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+                cull_radius(fmax(hl, h));
+                walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox,
+                                                                                int oy, int oz) {
                     R m;
                     const auto c = cand(j, jx, jy, jz, ox, oy, oz, m);
                     R dx, dy, dz;
@@ -568,6 +693,22 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
         const R Ai = fc[p], ci = fc[n + p], hinvi = fc[2 * n + p], normi = fc[3 * n + p];
         const R Hi = (R)2 * hi;
         const R H2i = Hi * Hi;
+        // block culling: runs within reach of max(2 h_i, the run's largest 2h)
+        const double bx = box_pos<FP32>(xi, a.g, 0, kx), by = box_pos<FP32>(yi, a.g, 1, ky),
+                     bz = box_pos<FP32>(zi, a.g, 2, kz);
+        const double mrg = FP32 ? a.g.cmin * 0x1p-18 : 0.0;
+        auto keep = [&](const double* bnd, double sx, double sy, double sz) {
+            const double rr = fmax((double)Hi, bnd[6]) * (1.0 + 1e-6) + mrg;
+            return box_d2(bnd, bx, by, bz, sx, sy, sz) < rr * rr;
+        };
+        // a cell is within reach of max(2 h_i, its largest 2h); a row within
+        // reach of max(2 h_i, any cell's reach)
+        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        auto keep_cell = [&](double d2, int key) {
+            const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
+            const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
+            return d2 < rr * rr;
+        };
 
         // ---- build: the pairs r < 2 max(h_i, h_j) (and coincident j != i), in window order
         int32_t* L = a.list + p;
@@ -582,7 +723,8 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
             r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
             return r2 < fmax(H2i, fc[4 * n + j]);
         };
-        walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox, int oy,
+                                                                        int oz) {
             R dx, dy, dz, r2;
             Loc<DIRECT> lj;
             if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj)) {
@@ -658,7 +800,8 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
             }
         } else {
             // more pairs than the list holds: the same pairs in the same order, from the window
-            walk_window(a, kx, ky, kz, r, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+            walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox,
+                                                                            int oy, int oz) {
                 R dx, dy, dz, r2;
                 Loc<DIRECT> lj;
                 if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj) && r2 > (R)0)
@@ -755,6 +898,20 @@ hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kern
     }
     if (fp32) SPHV_LIST_CASE(k_density_list, false, true, 1);
     SPHV_LIST_CASE(k_density_list, false, false, 1);
+}
+
+hipError_t launch_block_bounds(const PairArgs& a, double* blocks, int direct, int fp32, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((a.n + kBlock - 1) / kBlock);
+    if (direct) {
+        if (fp32) hipLaunchKernelGGL((k_block_bounds<true, true>), dim3(nb), dim3(kWave), 0, s, a, blocks);
+        else hipLaunchKernelGGL((k_block_bounds<true, false>), dim3(nb), dim3(kWave), 0, s, a, blocks);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_block_bounds<false, true>), dim3(nb), dim3(kWave), 0, s, a, blocks);
+        else hipLaunchKernelGGL((k_block_bounds<false, false>), dim3(nb), dim3(kWave), 0, s, a, blocks);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_t s)

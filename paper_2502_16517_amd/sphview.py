@@ -38,7 +38,8 @@ EXPORTS = [
     "sphv_status_string", "sphv_version", "sphv_params_init", "sphv_state_bytes", "sphv_state_init",
     "sphv_begin_step", "sphv_read_state", "sphv_write_state", "sphv_cells_workspace_bytes", "sphv_cells_create",
     "sphv_cells_build", "sphv_cells_get_info", "sphv_cells_destroy", "sphv_view_workspace_bytes",
-    "sphv_view_create", "sphv_aos_to_soa", "sphv_soa_to_aos", "sphv_view_field", "sphv_view_destroy",
+    "sphv_view_create", "sphv_aos_to_soa", "sphv_aos_to_soa_prefetch", "sphv_soa_to_aos", "sphv_view_field",
+    "sphv_view_destroy",
     "sphv_sph_density", "sphv_sph_force", "sphv_step_reduce", "sphv_kick_drift", "sphv_graph_begin", "sphv_graph_end",
     "sphv_graph_launch", "sphv_graph_destroy", "sphv_autotune_candidates", "sphv_autotune_workspace_bytes",
     "sphv_autotune", "sphv_records_sort_workspace_bytes", "sphv_records_sort", "sphv_records_sort_static",
@@ -119,6 +120,7 @@ def lib():
         "sphv_view_create": (C.c_int32, [C.POINTER(VP), C.POINTER(Descriptor), C.c_int64, C.POINTER(Layout),
                                          C.c_int32, VP, VP, VP, C.c_size_t]),
         "sphv_aos_to_soa": (C.c_int32, [VP, VP, VP]),
+        "sphv_aos_to_soa_prefetch": (C.c_int32, [VP, VP, VP]),
         "sphv_soa_to_aos": (C.c_int32, [VP, VP]),
         "sphv_view_field": (C.c_int32, [VP, C.c_uint32, C.POINTER(VP), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
@@ -362,6 +364,11 @@ def aos_to_soa(view, cells=None, stream=None):
     _chk(lib().sphv_aos_to_soa(view, cells, _stream(stream)), "aos_to_soa")
 
 
+def aos_to_soa_prefetch(view, cells=None, stream=None):
+    """Gathers ahead the read-only members no open view writes (see the header)."""
+    _chk(lib().sphv_aos_to_soa_prefetch(view, cells, _stream(stream)), "aos_to_soa_prefetch")
+
+
 def soa_to_aos(view, stream=None):
     _chk(lib().sphv_soa_to_aos(view, _stream(stream)), "soa_to_aos")
 
@@ -513,7 +520,7 @@ class Stepper:
     def __init__(self, rec: np.ndarray, params: Params, precision: int = PREC_FP64,
                  layout_density: Layout | None = None, layout_force: Layout | None = None,
                  device="cuda", aos=None, stream=None, sort_records: bool = False, merged: bool = False,
-                 record_ptrs=None):
+                 record_ptrs=None, overlap: bool = False):
         import torch
         self.torch = torch
         self.ptrs = record_ptrs
@@ -524,6 +531,11 @@ class Stepper:
         self.p = params
         self.precision = precision
         self.merged = merged
+        # overlap: the force view's read-only members are prefetched on a side
+        # stream (default priority) while the density loop runs
+        self.overlap = overlap and not merged
+        self.side = torch.cuda.Stream() if self.overlap else None
+        self.pref_ev = torch.cuda.Event() if self.overlap else None
         if merged and precision != PREC_FP64:
             raise ValueError("a merged view is FP64: the FP32 force loop stages its members as floats, which a "
                              "view stores only for members it does not write")
@@ -574,13 +586,31 @@ class Stepper:
             nb = records_sort_workspace_bytes(inputs.STRIDE, self.n)
             self.sort_ws = self.torch.empty(max(256, nb), dtype=self.torch.uint8, device=self.device)
 
+    def _main(self):
+        return self.stream if self.stream is not None else self.torch.cuda.current_stream()
+
+    def prefetch(self):
+        """With overlap (after the density view opened, so that the members it
+        writes are left out): the force view's other read-only members are
+        gathered on the side stream, concurrently with the density loop."""
+        if not self.overlap:
+            return
+        ev = self.torch.cuda.Event()
+        ev.record(self._main())
+        self.side.wait_event(ev)
+        aos_to_soa_prefetch(self.v_force, self.cells, self.side)
+        self.pref_ev.record(self.side)
+
     def density(self):
         aos_to_soa(self.v_dens, self.cells, self.stream)
+        self.prefetch()
         sph_density(self.v_dens, self.cells, self.p, self.state, self.stream)
         if not self.merged:
             soa_to_aos(self.v_dens, self.stream)
 
     def force(self):
+        if self.overlap:
+            self._main().wait_event(self.pref_ev)
         if not self.merged:
             aos_to_soa(self.v_force, self.cells, self.stream)
         sph_force(self.v_force, self.cells, self.p, self.state, self.stream)

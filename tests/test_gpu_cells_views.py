@@ -17,6 +17,8 @@ WORKLOADS = {
     "tube16": lambda: inputs.two_state_tube(16, 7),
     "kh24": lambda: inputs.kelvin_helmholtz(24, 9),
     "plummer8k": lambda: inputs.plummer(8192, 5, cell=0.1),
+    # 2^20 particles in cells of 0.02: thousands of cells of more than 64
+    "plummer1M": lambda: inputs.config4(),
 }
 
 
@@ -38,8 +40,9 @@ def test_cells_build_exact(orc, name):
     p = sv.params_for(w)
     c = w.rec
     ref_key = orc.bin_keys(c[:, S["x"]], c[:, S["y"]], c[:, S["z"]], w.lo, list(p.inv_cell), w.grid)
+    ref_sub = orc.sub_keys(c[:, S["x"]], c[:, S["y"]], c[:, S["z"]], w.lo, list(p.inv_cell), w.grid)
     nc = w.grid[0] * w.grid[1] * w.grid[2]
-    ref_perm, ref_start = orc.sort_cells(ref_key, nc)
+    ref_perm, ref_start = orc.sort_cells(ref_key, nc, ref_sub)
     assert np.array_equal(key, ref_key)
     assert np.array_equal(start, ref_start)
     assert np.array_equal(perm, ref_perm)

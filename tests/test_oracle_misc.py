@@ -248,3 +248,70 @@ def test_plummer_radial_distribution():
     assert r.max() <= 1.0
     # isotropy: mean direction near zero
     assert abs(np.mean(w.rec[:, S["z"]] / r)) < 0.03
+
+
+# ------------------------------------------------- second level of dense cells
+
+def test_sub_keys_by_hand(orc):
+    """Sub-cell codes computed by hand: a unit grid of 2 cells per axis on
+    [0, 2)^3 (cell 1, 16 sub-cells of 1/16 per axis)."""
+    assert orc.SUB_BITS == 4
+    # x in cell 1 at 1 + 5/16 (sub 5 = 0101b), y at 3/16 (sub 3 = 0011b), z at
+    # 1 + 15/16 + tiny (sub 15 = 1111b): bits interleave x0 y0 z0 x1 y1 z1 ...
+    x, y, z = np.array([1 + 5 / 16]), np.array([3 / 16]), np.array([1 + 15 / 16 + 1e-9])
+    code = int(orc.sub_keys(x, y, z, (0, 0, 0), (1, 1, 1), (2, 2, 2))[0])
+    sx, sy, sz = 5, 3, 15
+    expect = 0
+    for b in range(4):
+        expect |= ((sx >> b) & 1) << (3 * b)
+        expect |= ((sy >> b) & 1) << (3 * b + 1)
+        expect |= ((sz >> b) & 1) << (3 * b + 2)
+    assert code == expect == 0b100_101_110_111   # z3 y3 x3 | z2 y2 x2 | z1 y1 x1 | z0 y0 x0
+    # the corner of a cell is sub-cell 0; just below the next cell is all ones
+    c0 = orc.sub_keys(np.array([1.0]), np.array([1.0]), np.array([0.0]), (0, 0, 0), (1, 1, 1), (2, 2, 2))
+    c1 = orc.sub_keys(np.array([1 - 1e-12]), np.array([2 - 1e-12]), np.array([0.999999]), (0, 0, 0), (1, 1, 1),
+                      (2, 2, 2))
+    assert int(c0[0]) == 0 and int(c1[0]) == 4095
+    # outside an open box: clamped into the edge sub-cell
+    c2 = orc.sub_keys(np.array([-0.5]), np.array([2.5]), np.array([0.5]), (0, 0, 0), (1, 1, 1), (2, 2, 2))
+    sx, sy, sz = 0, 15, 8
+    e2 = 0
+    for b in range(4):
+        e2 |= ((sx >> b) & 1) << (3 * b) | ((sy >> b) & 1) << (3 * b + 1) | ((sz >> b) & 1) << (3 * b + 2)
+    assert int(c2[0]) == e2
+
+
+def test_dense_cells_ordered_by_sub_cell(orc):
+    """Cells of more than 64 particles are ordered by sub-cell code, ties by
+    index; other cells keep index order; a brute-force sort agrees, the cell
+    offsets are those of the plain sort, and consecutive runs of 64 inside a
+    dense cell are compact (a small box) while index order is not."""
+    rng = np.random.default_rng(11)
+    n = 6000
+    grid, lo, L = (3, 3, 3), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    inv = tuple(g / l for g, l in zip(grid, L))
+    # most particles crowd into the centre cell, the rest spread thinly
+    centre = rng.random(n) < 0.8
+    x, y, z = (np.where(centre, rng.uniform(1 / 3, 2 / 3, n), rng.uniform(0, 1, n)) for _ in range(3))
+    keys = orc.bin_keys(x, y, z, lo, inv, grid)
+    sub = orc.sub_keys(x, y, z, lo, inv, grid)
+    ncell = 27
+    perm, start = orc.sort_cells(keys, ncell, sub)
+    p0, s0 = orc.sort_cells(keys, ncell)
+    assert np.array_equal(start, s0)
+    counts = np.diff(start)
+    expect = sorted(range(n), key=lambda i: (keys[i], sub[i] if counts[keys[i]] > 64 else 0, i))
+    assert perm.tolist() == expect
+    assert counts.max() > 64 and (counts[(counts > 0) & (counts <= 64)]).size > 0
+    for c in range(ncell):
+        seg = perm[start[c]:start[c + 1]]
+        if counts[c] > 64:
+            assert np.all(np.diff(sub[seg]) >= 0)
+        else:
+            assert np.array_equal(seg, np.sort(seg))
+    c = int(np.argmax(counts))
+    seg = perm[start[c]:start[c + 1]]
+    ext = lambda ids: max(np.ptp(x[ids]), np.ptp(y[ids]), np.ptp(z[ids]))
+    runs = [ext(seg[k:k + 64]) for k in range(0, len(seg) - 63, 64)]
+    plain = [ext(np.sort(seg)[k:k + 64]) for k in range(0, len(seg) - 63, 64)]
+    assert np.mean(runs) < 0.5 * np.mean(plain)
