@@ -279,9 +279,9 @@ __global__ void k_place(const int32_t* key, int64_t n, int32_t* cursor, int32_t*
     if (valid) perm_tmp[base + lane - head] = (int32_t)i;
 }
 
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 128;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kSortLds = 2048;       // per-wave LDS capacity (ints)
+constexpr int kSortLds = 2048;       // per-wave LDS capacity (64-bit keys), a power of two
 
 // One wave per pair of cells (grid-stride): order each cell's record indices
 // ascending, which, since the indices are distinct, is the stable order of the
@@ -294,11 +294,10 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
                                                           const uint32_t* hmax_bits, int32_t* reach_d,
                                                           Geom g, int64_t nc)
 {
-    __shared__ int lds[kSortWaves][kSortLds];
-    __shared__ uint16_t lsub[kSortWaves][kSortLds];
+    __shared__ uint64_t lds[kSortWaves][kSortLds];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    int* buf = lds[w];
+    uint64_t* buf = lds[w];
     int64_t wave_id = (int64_t)blockIdx.x * kSortWaves + w;
     int64_t nwaves = (int64_t)gridDim.x * kSortWaves;
     auto reach_of = [&](int64_t c, int cnt) {
@@ -323,24 +322,39 @@ __global__ __launch_bounds__(kSortThreads) void k_segsort(const int32_t* cell_st
                 key_sorted[b + lane] = (int32_t)c;
             }
         } else if (cnt <= kSortLds) {
-            // a dense cell: rank by (sub-cell code, index)
-            uint16_t* bsub = lsub[w];
-            for (int k = lane; k < cnt; k += kWave) {
-                const int v = perm_tmp[b + k];
-                buf[k] = v;
-                bsub[k] = (uint16_t)sub[v];
+            // a dense cell: bitonic sort of the keys (sub-cell code, index) in
+            // LDS, padded to a power of two with keys above every real one
+            int pw = kWave;
+            while (pw < cnt) pw <<= 1;
+            for (int k = lane; k < pw; k += kWave) {
+                uint64_t key = ~0ull;
+                if (k < cnt) {
+                    const int v = perm_tmp[b + k];
+                    key = ((uint64_t)(uint32_t)sub[v] << 32) | (uint32_t)v;
+                }
+                buf[k] = key;
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_s_waitcnt(0);
-            for (int k = lane; k < cnt; k += kWave) {
-                const int v = buf[k];
-                const int sv = bsub[k];
-                int rank = 0;
-                for (int t = 0; t < cnt; ++t) {
-                    const int st = bsub[t];
-                    rank += (st < sv || (st == sv && buf[t] < v)) ? 1 : 0;
+            for (int kk = 2; kk <= pw; kk <<= 1) {
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int i = lane; i < pw; i += kWave) {
+                        const int l = i ^ jj;
+                        if (l > i) {
+                            const uint64_t x = buf[i], y = buf[l];
+                            const bool up = (i & kk) == 0;
+                            if ((x > y) == up) {
+                                buf[i] = y;
+                                buf[l] = x;
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_s_waitcnt(0);
                 }
-                perm[b + rank] = v;
+            }
+            for (int k = lane; k < cnt; k += kWave) {
+                perm[b + k] = (int32_t)(uint32_t)(buf[k] & 0xffffffffull);
                 key_sorted[b + k] = (int32_t)c;
             }
             __builtin_amdgcn_wave_barrier();
@@ -778,7 +792,7 @@ hipError_t launch_cells_build(const CellsDev& c, const FieldRef* f, const Access
         hipLaunchKernelGGL(k_place, dim3(nblk(c.n, 256)), dim3(256), 0, s, c.key, c.n, c.cursor, c.perm_tmp);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    unsigned sb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((c.nc + 1) / 2 + kSortWaves - 1) / kSortWaves, 8192));
+    unsigned sb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((c.nc + 1) / 2 + kSortWaves - 1) / kSortWaves, 16384));
     hipLaunchKernelGGL(k_segsort, dim3(sb), dim3(kSortThreads), 0, s, c.cell_start, c.perm_tmp, c.sub, c.perm,
                        c.key_sorted, c.hmax_bits, c.reach_d, g, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
