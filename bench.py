@@ -126,6 +126,9 @@ WORKLOADS = {
 }
 PKW = {}
 HOST_RECORDS = False
+# neighbour-list capacity of the list walks (the lattices' lists hold at most
+# 81 entries, the Plummer sphere's about 60)
+LIST_CAP = 128
 # smoothing kernels (the library's kernel ids)
 KERNELS = {"cubic": 0, "quartic": 1}
 
@@ -449,6 +452,9 @@ def main():
     ap.add_argument("--list-cap", type=int, default=0,
                     help="neighbour-list capacity per particle: > 0 runs both pair loops as list walks "
                          "(one lane per particle), 0 the item kernels over cell windows")
+    ap.add_argument("--symmetric", action="store_true",
+                    help="with --list-cap: the force loop evaluates each pair once (Newton's third law) and "
+                         "stores the partner's side")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic kernel for "
                          "scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -486,6 +492,7 @@ def main():
     PKW.update(pkw)
     PKW["kernel"] = KERNELS[args.kernel]
     PKW["list_cap"] = args.list_cap
+    PKW["symmetric"] = 1 if args.symmetric else 0
     log(f"[bench] generating the workload: {desc}")
     w = getattr(inputs, gen)()
     if args.host_records:
@@ -576,9 +583,16 @@ def main():
         kern, flops, ms_k = "density", dens_flops, r64["ms_density"]
     achieved = flops / (ms_k / 1e3) / 1e12
     choice = choice_of(sv, t64)
-    tr = measured_traffic(choice) if args.kernel == "cubic" else {}
+    # the committed counters are those of the item kernels
+    tr = measured_traffic(choice) if args.kernel == "cubic" and args.list_cap == 0 else {}
     traffic, traffic_layout = tr.get(kern, (None, None))
-    roofline = {"bound": "alu", "kernel": f"sph_{kern} (fp64 pair loop, {choice[kern + '_layout']})",
+    if args.list_cap == 0:
+        form = f"fp64 pair loop, {choice[kern + '_layout']}"
+    elif kern == "force" and args.symmetric:
+        form = f"fp64 symmetric list walk, list_cap {args.list_cap}"
+    else:
+        form = f"fp64 list walk, list_cap {args.list_cap}"
+    roofline = {"bound": "alu", "kernel": f"sph_{kern} ({form})",
                 "achieved": achieved,
                 "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VALU / 1e12),
                 "traffic": traffic,
@@ -736,9 +750,11 @@ def persistent_form(torch, sv, inputs, w, args):
 
 def batched_form(torch, sv, inputs, args):
     """The batching form on the 2^20-particle Plummer sphere (cells of 1 to
-    ~2000 particles): FP32 pairs, the whole step replayed as one HIP graph,
-    against the plain FP64 GPU form (eager) on the same records.  SoA views
-    with the automatic tile shape (no tuning: a trial there costs a step)."""
+    ~2000 particles, dense cells ordered by sub-cell): neighbour-list walks
+    that skip cells and 64-particle runs out of reach, FP32 pairs, the whole
+    step replayed as one HIP graph; against the plain FP64 GPU form (the item
+    kernels over cell windows, eager) on the same records, and the FP64 list
+    walks.  SoA views (no tuning: a trial there costs a step)."""
     gen, pkw, desc = WORKLOADS["plummer1M"]
     saved = dict(PKW)
     PKW.clear()
@@ -748,21 +764,28 @@ def batched_form(torch, sv, inputs, args):
     w = getattr(inputs, gen)()
     lay = (tuple(w.grid), sv.layout(), sv.layout())
     steps, warm = args.batched_steps, 2
-    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, lay)
-    r64 = run_timed(torch, sv, st, steps, warm)
-    st.close()
-    st = make_stepper(torch, sv, inputs, w, sv.PREC_FP32, lay)
-    r32 = run_timed(torch, sv, st, steps, warm, graph=True)
-    st.close()
+    runs = {}
+    for name, prec, cap, graph in (("fp64_items_eager", sv.PREC_FP64, 0, False),
+                                   ("fp64_lists_eager", sv.PREC_FP64, LIST_CAP, False),
+                                   ("fp32_lists_graph", sv.PREC_FP32, LIST_CAP, True)):
+        log(f"[bench]   {name}")
+        PKW["list_cap"] = cap
+        st = make_stepper(torch, sv, inputs, w, prec, lay)
+        r = run_timed(torch, sv, st, steps, warm, graph=graph)
+        st.close()
+        runs[name] = {"value": r["pairs"] / (r["ms_total"] / 1e3), "ms_per_step": r["ms_total"] / steps,
+                      "flags": r["flags"]}
+        if not graph:
+            runs[name].update(ms_density=r["ms_density"], ms_force=r["ms_force"], ms_cells=r["ms_cells"])
     PKW.clear()
     PKW.update(saved)
-    v64 = r64["pairs"] / (r64["ms_total"] / 1e3)
-    v32 = r32["pairs"] / (r32["ms_total"] / 1e3)
-    return {"workload": "plummer1M", "n": w.n, "steps": steps, "layout": "soa/tpiauto/branch",
-            "value": v32, "ms_per_step": r32["ms_total"] / steps, "flags": r32["flags"],
-            "fp64_eager": {"value": v64, "ms_per_step": r64["ms_total"] / steps, "flags": r64["flags"],
-                           "ms_density": r64["ms_density"], "ms_force": r64["ms_force"]},
-            "speedup_vs_fp64": v32 / v64}
+    b = runs["fp32_lists_graph"]
+    base = runs["fp64_items_eager"]
+    return {"workload": "plummer1M", "n": w.n, "steps": steps, "layout": "soa, list walks (cap %d)" % LIST_CAP,
+            "value": b["value"], "ms_per_step": b["ms_per_step"], "flags": b["flags"],
+            "fp64_eager": base, "fp64_lists_eager": runs["fp64_lists_eager"],
+            "speedup_vs_fp64": b["value"] / base["value"],
+            "speedup_lists_fp64_vs_items_fp64": runs["fp64_lists_eager"]["value"] / base["value"]}
 
 
 if __name__ == "__main__":

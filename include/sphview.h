@@ -80,6 +80,8 @@ enum {
     SPHV_F_QUEUE_OVERFLOW = 1u << 3,   /* work items exceeded the planned capacity      */
     SPHV_F_NONFINITE_OUTPUT = 1u << 4, /* NaN/inf density or force result               */
     SPHV_F_GRID_TOO_SMALL = 1u << 5,   /* a reach window wraps onto itself (periodic)   */
+    SPHV_F_LIST_MISMATCH = 1u << 7,    /* symmetric force: a pair in one particle's list */
+                                       /* but not its partner's (never expected)        */
     SPHV_F_OUT_OF_BOX = 1u << 6        /* a particle lies outside an open box, or       */
                                        /* outside [lo, lo+len) on a periodic axis: the  */
                                        /* records must hold wrapped coordinates (such a */
@@ -167,7 +169,8 @@ typedef struct {
     int32_t list_cap;  /* 0: the pair loops walk cell windows per work item; 1..4096: */
                        /* they walk per-particle neighbour lists of at most list_cap */
                        /* entries (the cells workspace holds them; see below)       */
-    int32_t reserved;
+    int32_t symmetric; /* 1 (with list_cap > 0, FP64): the force loop evaluates each */
+                       /* pair once (Newton's third law), see below; 0: twice        */
 } sphv_params;
 
 /* Smoothing kernels W(r, h) = w(q) / (pi h^3), q = r/h, both with support
@@ -193,8 +196,19 @@ enum { SPHV_KERNEL_CUBIC = 0, SPHV_KERNEL_QUARTIC = 1 };
  * tpi and masked do not apply to list walks (every list entry is evaluated,
  * out-of-range density entries as the neutral element).  The lists need
  * list_cap * n * 4 bytes of the cells workspace.
+ * Symmetric pairs (symmetric = 1; paper Sec. 5.3, F(p1, p2) = -F(p2, p1)): the
+ * force lists hold each particle's pairs in ascending sorted position; a first
+ * pass evaluates each pair (i, j), i < j, once, adds i's side to i and stores
+ * j's side (its acceleration and du/dt terms and the pair's v_sig) in j's slot
+ * for i, found by bisection in j's list; a second pass adds, per particle, the
+ * stored sides of its partners below it in list order, after the sum over
+ * those above it.  Every sum has a fixed order, so results are deterministic;
+ * they differ from the twice-evaluated form in rounding only.  The slots take
+ * 40 * list_cap * n bytes of the cells workspace.  Should any list overflow,
+ * the second pass evaluates every particle's pairs twice from its window.
+ * FP32 views fail with SPHV_E_UNSUPPORTED.
  * Defaults: gamma 5/3, eta 1.2, cfl 0.3, h_tol 1e-13, headroom 1.1, max_iter 16,
- * kernel SPHV_KERNEL_CUBIC, list_cap 0. */
+ * kernel SPHV_KERNEL_CUBIC, list_cap 0, symmetric 0. */
 int32_t sphv_params_init(sphv_params* p, const double lo[3], const double len[3],
                          const int32_t grid[3], const int32_t periodic[3]);
 

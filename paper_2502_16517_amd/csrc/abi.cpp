@@ -105,7 +105,7 @@ bool finite_params(const sphv_params* p)
     return std::isfinite(p->gamma) && p->gamma > 1.0 && p->eta > 0.0 && p->cfl > 0.0 &&
            p->h_tol >= 0.0 && p->headroom >= 1.0 && p->max_iter >= 1 && p->max_iter <= 64 &&
            (p->kernel == SPHV_KERNEL_CUBIC || p->kernel == SPHV_KERNEL_QUARTIC) && p->list_cap >= 0 &&
-           p->list_cap <= kMaxListCap;
+           p->list_cap <= kMaxListCap && (p->symmetric == 0 || (p->symmetric == 1 && p->list_cap > 0));
 }
 
 Geom geom_of(const sphv_params* p)
@@ -264,7 +264,7 @@ Access acc_rec(const int32_t* index, const sphv_descriptor& d, const void* aos)
 }
 
 // Cells workspace carving (all arrays 256-B aligned).
-uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t list_cap)
+uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t list_cap, int32_t symmetric)
 {
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) { char* p = base ? base + off : nullptr; off = align_up(off + bytes, kAlign); return p; };
@@ -297,6 +297,9 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t lis
     c->list = list_cap > 0 ? (int32_t*)take(4 * (uint64_t)list_cap * (uint64_t)std::max<int64_t>(n, 1)) : nullptr;
     c->fconst = (double*)take(5 * 8 * (uint64_t)std::max<int64_t>(n, 1));
     c->blocks = list_cap > 0 ? (double*)take(8ull * kBlockWords * (uint64_t)(n / kBlock + 1)) : nullptr;
+    c->list_len = list_cap > 0 ? (int32_t*)take(4 * (uint64_t)std::max<int64_t>(n, 1)) : nullptr;
+    c->slots = list_cap > 0 && symmetric
+                   ? (double*)take(5 * 8 * (uint64_t)list_cap * (uint64_t)std::max<int64_t>(n, 1)) : nullptr;
     c->n = n;
     c->nc = nc;
     c->max_items = max_items;
@@ -480,7 +483,7 @@ size_t sphv_cells_workspace_bytes(int64_t n, const sphv_params* p)
     if (!p || n < 0 || !finite_params(p)) return 0;
     int64_t nc = (int64_t)p->grid[0] * p->grid[1] * p->grid[2];
     CellsDev c{};
-    return (size_t)carve_cells(&c, nullptr, n, nc, p->list_cap);
+    return (size_t)carve_cells(&c, nullptr, n, nc, p->list_cap, p->symmetric);
 }
 
 int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p, void* ws, size_t ws_bytes)
@@ -493,11 +496,11 @@ int32_t sphv_cells_create(sphv_cells** out, int64_t n, const sphv_params* p, voi
     if (nc > INT32_MAX / 2) return SPHV_E_UNSUPPORTED;
     if ((uintptr_t)ws % kAlign) return SPHV_E_WORKSPACE;
     CellsDev c{};
-    uint64_t need_b = carve_cells(&c, nullptr, n, nc, p->list_cap);
+    uint64_t need_b = carve_cells(&c, nullptr, n, nc, p->list_cap, p->symmetric);
     if (ws_bytes < need_b) return SPHV_E_WORKSPACE;
     sphv_cells* h = new (std::nothrow) sphv_cells;
     if (!h) return SPHV_E_INVALID_ARG;
-    carve_cells(&h->dev, (char*)ws, n, nc, p->list_cap);
+    carve_cells(&h->dev, (char*)ws, n, nc, p->list_cap, p->symmetric);
     h->params = *p;
     *out = h;
     return SPHV_OK;
@@ -911,6 +914,8 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
     PairArgs a;
     int32_t s = pair_setup(v, c, p, state, in, 12, 12, out, 5, &a);
     if (s) return s;
+    // each pair once: the FP64 list walks only
+    if (c->dev.slots && v->precision == SPHV_PREC_FP32) return SPHV_E_UNSUPPORTED;
     if (c->params.grid[0] != p->grid[0] || c->params.grid[1] != p->grid[1] || c->params.grid[2] != p->grid[2])
         return SPHV_E_INVALID_ARG;
     if (v->n == 0) return SPHV_OK;
@@ -942,6 +947,11 @@ int32_t sphv_sph_force(sphv_view* v, const sphv_cells* c, const sphv_params* p, 
             return SPHV_E_HIP;
         a.blocks = c->dev.blocks;
         a.cell_h = c->dev.hmax_f;
+        a.list_len = c->dev.list_len;
+        if (c->dev.slots) {
+            a.slots = c->dev.slots;
+            return hip_status(launch_force_sym(a, direct, p->kernel, st));
+        }
         return hip_status(launch_force_list(a, direct, v->precision == SPHV_PREC_FP32, p->kernel, st));
     }
     return hip_status(launch_force(a, direct, v->precision == SPHV_PREC_FP32, (int)v->layout.masked, p->kernel, st));

@@ -96,6 +96,8 @@ struct CellsDev {
     int32_t* list;         // [list_cap][n] neighbour lists (list walks only, else null)
     double* fconst;        // [5][n] per-particle force constants (of the pair precision)
     double* blocks;        // [n / 64 + 1][kBlockWords] bounds of each run of 64 sorted positions (list walks)
+    int32_t* list_len;     // [n] entries of each particle's list (list walks)
+    double* slots;         // [5][list_cap][n] symmetric force: the stored j sides (else null)
     int32_t list_cap;
     int32_t pad_l;
     int64_t n;
@@ -109,6 +111,7 @@ enum {
     META_MASKS = 2,                          // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
     META_RGLOBAL_F = 3,                      // largest own force reach
     META_SCAN = 4,                           // block tickets of the scans of cells_build (two slots)
+    META_SYM_OVF = 6,                        // symmetric force: some list overflowed
     META_QHEAD_D = kQStride,                       // 8 per-XCD heads of the density queue, kQStride apart
     META_QHEAD_F = kQStride + kNumXcd * kQStride,  // the same for the force queue
     META_SIZE = kQStride + 2 * kNumXcd * kQStride
@@ -142,6 +145,8 @@ struct PairArgs {
     void* fconst;              // force: per-particle constants (R[5][n], R the pair precision)
     const double* blocks;      // list walks: bounds of each run of kBlock sorted positions, or null
     const uint32_t* cell_h;    // force list walk: float bits of each cell's largest 2h (rounded up)
+    int32_t* list_len;         // list walks: entries of each list
+    double* slots;             // symmetric force: stored j sides, slot (k, e, j) at k cap n + e n + j
     int32_t list_cap;
     int32_t pad3;
 };
@@ -168,6 +173,8 @@ hipError_t launch_force(const PairArgs& a, int direct, int fp32, int masked, int
 // the list walks (k_list.hip); each ends with the fold of its counters
 hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kernel, hipStream_t s);
 hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kernel, hipStream_t s);
+// the symmetric force (FP64 list walks): lists, one evaluation per pair, the stored sides
+hipError_t launch_force_sym(const PairArgs& a, int direct, int kernel, hipStream_t s);
 // per-particle constants of both force loops (k_list.hip), into a.fconst
 hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_t s);
 // bounds of each run of kBlock sorted positions into blocks (k_list.hip)

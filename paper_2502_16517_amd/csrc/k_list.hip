@@ -296,9 +296,29 @@ __device__ __forceinline__ double slab_dist(double p, int k, const Geom& g, int 
     return fmax(fmax(lo - p, p - (lo + g.cell[d])), 0.0);
 }
 
-// Walks the window of cell (kx, ky, kz) with per-axis reach r in a fixed order
-// (dz, dy, then the row's cells along x: wrapped left part, main part, wrapped
-// right part) and calls visit(j, jx, jy, jz, ox, oy, oz) for every candidate j
+// The window's offsets -r..r along an axis, taken from index t0 on (wrapping
+// round), visit the cells in ascending order of their wrapped index: on a
+// periodic axis whose window wraps, the offsets that wrap come last (low
+// wrap) or first (high wrap).
+__device__ __forceinline__ int rot_start(int k, int r, int n, int periodic)
+{
+    if (!periodic) return 0;
+    if (k - r < 0) return r - k;              // offset -k has cell 0
+    if (k + r >= n) return n - k + r;         // offset n-k wraps to cell 0
+    return 0;
+}
+
+__device__ __forceinline__ int rot_offset(int t, int t0, int r)
+{
+    int q = t + t0;
+    if (q > 2 * r) q -= 2 * r + 1;
+    return q - r;
+}
+
+// Walks the window of cell (kx, ky, kz) with per-axis reach r in a fixed
+// order, ascending in the cells' keys and so in sorted position (z, then y,
+// then x, each from the lowest wrapped index up), and calls
+// visit(j, jx, jy, jz, ox, oy, oz) for every candidate j
 // (sorted position) of cell (jx, jy, jz), (ox, oy, oz) being that cell's
 // offset from the local cell in the window.  Candidates that cannot be within
 // reach of the local particle at (px, py, pz) (box frame) are skipped, in the
@@ -313,14 +333,20 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
                                             double py, double pz, KC&& keep_cell, KB&& keep_block, V&& visit)
 {
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
-    for (int dz = -r[2]; dz <= r[2]; ++dz) {
+    // offsets in the order that visits cells (so sorted positions) ascending
+    const int t0z = rot_start(kz, r[2], nz, a.g.periodic[2]);
+    const int t0y = rot_start(ky, r[1], ny, a.g.periodic[1]);
+    const int t0x = rot_start(kx, r[0], nx, a.g.periodic[0]);
+    for (int tz = 0; tz <= 2 * r[2]; ++tz) {
+        const int dz = rot_offset(tz, t0z, r[2]);
         int z2 = kz + dz;
         if (z2 < 0 || z2 >= nz) {
             if (!a.g.periodic[2]) continue;
             z2 += z2 < 0 ? nz : -nz;
         }
         const double ez = slab_dist(pz, kz + dz, a.g, 2);
-        for (int dy = -r[1]; dy <= r[1]; ++dy) {
+        for (int ty = 0; ty <= 2 * r[1]; ++ty) {
+            const int dy = rot_offset(ty, t0y, r[1]);
             int y2 = ky + dy;
             if (y2 < 0 || y2 >= ny) {
                 if (!a.g.periodic[1]) continue;
@@ -330,7 +356,8 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
             const double dyz = fma(ey, ey, ez * ez);
             if (!keep_cell(dyz, -1)) continue;
             const int row = (z2 * ny + y2) * nx;
-            for (int dx = -r[0]; dx <= r[0]; ++dx) {
+            for (int tx = 0; tx <= 2 * r[0]; ++tx) {
+                const int dx = rot_offset(tx, t0x, r[0]);
                 int x2 = kx + dx;
                 if (x2 < 0 || x2 >= nx) {
                     if (!a.g.periodic[0]) continue;
@@ -845,6 +872,297 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
     }
 }
 
+// ======================================================= symmetric force
+//
+// Each pair evaluated once (paper Sec. 5.3: F(p1, p2) = -F(p2, p1)), FP64,
+// in three launches with a fixed order of every sum:
+//  1. k_force_sym_build: every particle's force list, ascending in sorted
+//     position (the window walk's order), and its length;
+//  2. k_force_sym_upper: for each pair (i, j) with i < j, the owner i evaluates
+//     it, adds its own side in list order, and stores j's side -- m_i B r_hat
+//     (B the pair's bracket A_i g_i + A_j g_j + Pi gbar), m_i (A_j g_j + Pi
+//     gbar / 2) w and the pair's v_sig -- in slot e of j, e being i's position
+//     in j's list (found by bisection); i's own sums go to its outputs;
+//  3. k_force_sym_lower: each particle adds the slots of its partners below
+//     it (the head of its list) in list order to what pass 2 left.
+// Should any list overflow (flagged by pass 1), pass 2 does nothing and pass
+// 3 evaluates every particle's pairs twice from its window.
+
+// Common set-up of one particle of the force loop (FP64).
+template <bool DIRECT>
+struct ForceLane {
+    double xi, yi, zi, vxi, vyi, vzi, hi, rhoi, hali, mi, Ai, ci, hinvi, normi, Hi, H2i, bx, by, bz;
+    int kx, ky, kz;
+    int r[3];
+    Loc<DIRECT> li;
+
+    __device__ __forceinline__ void load(const PairArgs& a, int64_t p, uint32_t& flags)
+    {
+        const int cell = a.key_sorted[p];
+        cell_coords(cell, a.g, kx, ky, kz);
+        lane_reach(a.g, a.reach[cell], r, flags);
+        li = locate<DIRECT>(a.acc, p);
+        xi = ld_f64(a.f[SPHV_X], li);
+        yi = ld_f64(a.f[SPHV_Y], li);
+        zi = ld_f64(a.f[SPHV_Z], li);
+        vxi = ld_f64(a.f[SPHV_VX], li);
+        vyi = ld_f64(a.f[SPHV_VY], li);
+        vzi = ld_f64(a.f[SPHV_VZ], li);
+        hi = ld_f64(a.f[SPHV_H], li);
+        rhoi = ld_f64(a.f[SPHV_RHO], li);
+        mi = ld_f64(a.f[SPHV_M], li);
+        hali = 0.5 * ld_f64(a.f[SPHV_ALPHA], li);
+        const double* fc = (const double*)a.fconst;
+        const int64_t n = a.n;
+        Ai = fc[p];
+        ci = fc[n + p];
+        hinvi = fc[2 * n + p];
+        normi = fc[3 * n + p];
+        Hi = 2.0 * hi;
+        H2i = Hi * Hi;
+        bx = xi;
+        by = yi;
+        bz = zi;
+    }
+};
+
+// One pair's terms from i's side (r > 0): B, the unit vector, w, gbar, visc,
+// g_i, g_j, vs.
+template <int KERN, bool DIRECT>
+struct PairTerms {
+    double B, ex, ey, ez, w, gbar, visc, gi, gj, vs, mj, Aj;
+
+    __device__ __forceinline__ void eval(const PairArgs& a, const ForceLane<DIRECT>& L, int j,
+                                         const Loc<DIRECT>& lj, double dx, double dy, double dz, double r2)
+    {
+        const double* fc = (const double*)a.fconst;
+        const int64_t n = a.n;
+        const double vxj = ld_f64(a.f[SPHV_VX], lj), vyj = ld_f64(a.f[SPHV_VY], lj), vzj = ld_f64(a.f[SPHV_VZ], lj);
+        mj = ld_f64(a.f[SPHV_M], lj);
+        const double rhoj = ld_f64(a.f[SPHV_RHO], lj);
+        const double halj = 0.5 * ld_f64(a.f[SPHV_ALPHA], lj);
+        Aj = fc[j];
+        const double cj = fc[n + j], hinvj = fc[2 * n + j], normj = fc[3 * n + j];
+        const double y = rsq_l(r2);
+        const double rr = r2 * y;
+        gi = spl_dw<KERN>(rr * L.hinvi) * L.normi;
+        gj = spl_dw<KERN>(rr * hinvj) * normj;
+        gbar = 0.5 * (gi + gj);
+        ex = dx * y;
+        ey = dy * y;
+        ez = dz * y;
+        w = (L.vxi - vxj) * ex + (L.vyi - vyj) * ey + (L.vzi - vzj) * ez;
+        const double mu = w < 0.0 ? w : 0.0;
+        vs = L.ci + cj - 3.0 * mu;
+        visc = -(L.hali + halj) * vs * mu * rcp_l(L.rhoi + rhoj);
+        B = fma(visc, gbar, fma(Aj, gj, L.Ai * gi));
+    }
+};
+
+template <bool DIRECT, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_sym_build(PairArgs a)
+{
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    const double* fc = (const double*)a.fconst;
+    unsigned long long n_pairs = 0;
+    uint32_t flags = 0;
+    bool over = false;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        ForceLane<DIRECT> L;
+        L.load(a, p, flags);
+        auto keep = [&](const double* bnd, double sx, double sy, double sz) {
+            const double rr = fmax(L.Hi, bnd[6]) * (1.0 + 1e-6);
+            return box_d2(bnd, L.bx, L.by, L.bz, sx, sy, sz) < rr * rr;
+        };
+        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        auto keep_cell = [&](double d2, int key) {
+            const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
+            const double rr = fmax(L.Hi, Hc) * (1.0 + 1e-6);
+            return d2 < rr * rr;
+        };
+        int32_t* Ls = a.list + p;
+        int len = 0, coinc = 0;
+        walk_window(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
+                    [&](int j, int, int, int, int, int, int) {
+                        const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                        const double dx = mi_diff(L.xi, ld_f64(a.f[SPHV_X], lj), a.g, 0);
+                        const double dy = mi_diff(L.yi, ld_f64(a.f[SPHV_Y], lj), a.g, 1);
+                        const double dz = mi_diff(L.zi, ld_f64(a.f[SPHV_Z], lj), a.g, 2);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < fmax(L.H2i, fc[4 * n + j])) {
+                            if (r2 > 0.0) {
+                                if (len < cap) Ls[(int64_t)len * n] = j;
+                                ++len;
+                            } else if (j != (int)p) {
+                                ++coinc;
+                            }
+                        }
+                    });
+        a.list_len[p] = len;
+        over |= len > cap;
+        n_pairs += (unsigned long long)(len + coinc);
+    }
+    if (__any(over) && lane == 0) atomicOr((unsigned int*)&a.meta[META_SYM_OVF], 1u);
+    for (int off = 32; off > 0; off >>= 1) {
+        n_pairs += __shfl_xor(n_pairs, off, kWave);
+        flags |= __shfl_xor(flags, off, kWave);
+    }
+    if (lane == 0) {
+        int64_t* pp = a.part + (int64_t)blockIdx.x * kPartSlots;
+        pp[0] = (int64_t)n_pairs;
+        pp[1] = 0;
+        pp[2] = 0;
+        pp[3] = flags;
+    }
+}
+
+template <bool DIRECT, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_sym_upper(PairArgs a)
+{
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t cn = (int64_t)a.list_cap * n;
+    if (a.meta[META_SYM_OVF]) return;
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        ForceLane<DIRECT> L;
+        L.load(a, p, flags);
+        const int32_t* Li = a.list + p;
+        const int len = a.list_len[p];
+        double pax = 0.0, pay = 0.0, paz = 0.0, pdu = 0.0, vsig = 2.0 * L.ci;
+        // the list ascends: the partners above p are its tail
+        for (int e = 0; e < len; ++e) {
+            const int j = Li[(int64_t)e * n];
+            if (j < (int)p) continue;
+            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+            const double dx = mi_diff(L.xi, ld_f64(a.f[SPHV_X], lj), a.g, 0);
+            const double dy = mi_diff(L.yi, ld_f64(a.f[SPHV_Y], lj), a.g, 1);
+            const double dz = mi_diff(L.zi, ld_f64(a.f[SPHV_Z], lj), a.g, 2);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            PairTerms<KERN, DIRECT> t;
+            t.eval(a, L, j, lj, dx, dy, dz, r2);
+            const double coef = t.mj * t.B;
+            pax = fma(-coef, t.ex, pax);
+            pay = fma(-coef, t.ey, pay);
+            paz = fma(-coef, t.ez, paz);
+            pdu = pdu + t.mj * fma(0.5 * t.visc, t.gbar, L.Ai * t.gi) * t.w;
+            vsig = t.vs > vsig ? t.vs : vsig;
+            // j's side, in j's slot for p: p's position in j's (ascending) list
+            const int32_t* Lj = a.list + j;
+            const int lenj = a.list_len[j];
+            int lo = 0, hi = lenj;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (Lj[(int64_t)mid * n] < (int)p) lo = mid + 1;
+                else hi = mid;
+            }
+            // the pair relation is symmetric, so p is in j's list; a miss is a
+            // fault of the lists, flagged, its slot left alone
+            if (lo >= lenj || Lj[(int64_t)lo * n] != (int)p) {
+                flags |= SPHV_F_LIST_MISMATCH;
+                continue;
+            }
+            const double cj = L.mi * t.B;
+            double* sl = a.slots + (int64_t)lo * n + j;
+            sl[0] = cj * t.ex;
+            sl[cn] = cj * t.ey;
+            sl[2 * cn] = cj * t.ez;
+            sl[3 * cn] = L.mi * fma(0.5 * t.visc, t.gbar, t.Aj * t.gj) * t.w;
+            sl[4 * cn] = t.vs;
+        }
+        st_f64(a.f[SPHV_AX], L.li, pax);
+        st_f64(a.f[SPHV_AY], L.li, pay);
+        st_f64(a.f[SPHV_AZ], L.li, paz);
+        st_f64(a.f[SPHV_UDT], L.li, pdu);
+        st_f64(a.f[SPHV_VSIG], L.li, vsig);
+    }
+    for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
+    if (lane == 0 && flags) atomicOr(&a.state->flags, flags);
+}
+
+template <bool DIRECT, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_sym_lower(PairArgs a)
+{
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t cn = (int64_t)a.list_cap * n;
+    const bool twice = a.meta[META_SYM_OVF] != 0;
+    const double* fc = (const double*)a.fconst;
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        ForceLane<DIRECT> L;
+        L.load(a, p, flags);
+        double ax, ay, az, du, vsig;
+        if (!twice) {
+            // the upper sums pass 2 left, then the stored sides of the partners below
+            const int32_t* Li = a.list + p;
+            const int len = a.list_len[p];
+            double lax = 0.0, lay = 0.0, laz = 0.0, ldu = 0.0;
+            vsig = ld_f64(a.f[SPHV_VSIG], L.li);
+            for (int e = 0; e < len; ++e) {
+                if (Li[(int64_t)e * n] > (int)p) break;
+                const double* sl = a.slots + (int64_t)e * n + p;
+                lax += sl[0];
+                lay += sl[cn];
+                laz += sl[2 * cn];
+                ldu += sl[3 * cn];
+                vsig = sl[4 * cn] > vsig ? sl[4 * cn] : vsig;
+            }
+            ax = ld_f64(a.f[SPHV_AX], L.li) + lax;
+            ay = ld_f64(a.f[SPHV_AY], L.li) + lay;
+            az = ld_f64(a.f[SPHV_AZ], L.li) + laz;
+            du = ld_f64(a.f[SPHV_UDT], L.li) + ldu;
+        } else {
+            // some list overflowed: every pair of p from its window, evaluated here
+            auto keep = [&](const double* bnd, double sx, double sy, double sz) {
+                const double rr = fmax(L.Hi, bnd[6]) * (1.0 + 1e-6);
+                return box_d2(bnd, L.bx, L.by, L.bz, sx, sy, sz) < rr * rr;
+            };
+            const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+            auto keep_cell = [&](double d2, int key) {
+                const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
+                const double rr = fmax(L.Hi, Hc) * (1.0 + 1e-6);
+                return d2 < rr * rr;
+            };
+            ax = ay = az = du = 0.0;
+            vsig = 2.0 * L.ci;
+            walk_window(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
+                        [&](int j, int, int, int, int, int, int) {
+                            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                            const double dx = mi_diff(L.xi, ld_f64(a.f[SPHV_X], lj), a.g, 0);
+                            const double dy = mi_diff(L.yi, ld_f64(a.f[SPHV_Y], lj), a.g, 1);
+                            const double dz = mi_diff(L.zi, ld_f64(a.f[SPHV_Z], lj), a.g, 2);
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            if (!(r2 < fmax(L.H2i, fc[4 * n + j]) && r2 > 0.0)) return;
+                            PairTerms<KERN, DIRECT> t;
+                            t.eval(a, L, j, lj, dx, dy, dz, r2);
+                            const double coef = t.mj * t.B;
+                            ax = fma(-coef, t.ex, ax);
+                            ay = fma(-coef, t.ey, ay);
+                            az = fma(-coef, t.ez, az);
+                            du = du + t.mj * fma(0.5 * t.visc, t.gbar, L.Ai * t.gi) * t.w;
+                            vsig = t.vs > vsig ? t.vs : vsig;
+                        });
+        }
+        st_f64(a.f[SPHV_AX], L.li, ax);
+        st_f64(a.f[SPHV_AY], L.li, ay);
+        st_f64(a.f[SPHV_AZ], L.li, az);
+        st_f64(a.f[SPHV_UDT], L.li, du);
+        st_f64(a.f[SPHV_VSIG], L.li, vsig);
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(du))) flags |= SPHV_F_NONFINITE_OUTPUT;
+    }
+    for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
+    if (lane == 0 && flags) atomicOr(&a.state->flags, flags);
+}
+
 // Workgroups (one wave each) that the device holds at once for a kernel, a
 // multiple of the 8 XCDs, at most kMaxPairBlocks; queried once per kernel.
 template <class K>
@@ -926,6 +1244,42 @@ hipError_t launch_force_prep(const PairArgs& a, int direct, int fp32, hipStream_
         else hipLaunchKernelGGL((k_force_prep<false, false>), dim3(nb), dim3(256), 0, s, a);
     }
     return hipGetLastError();
+}
+
+template <bool DIRECT, int KERN>
+static hipError_t run_force_sym(std::atomic<int>* caches, const PairArgs& a0, hipStream_t s)
+{
+    PairArgs a = a0;
+    hipError_t e = launch_fill_u32(a.meta + META_SYM_OVF, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    a.nblocks = list_blocks(k_force_sym_build<DIRECT, KERN>, caches[0], a.n);
+    hipLaunchKernelGGL((k_force_sym_build<DIRECT, KERN>), dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_pair_fold(a, a.nblocks, 0, s)) != hipSuccess) return e;
+    const int nb2 = list_blocks(k_force_sym_upper<DIRECT, KERN>, caches[1], a.n);
+    hipLaunchKernelGGL((k_force_sym_upper<DIRECT, KERN>), dim3((unsigned)nb2), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nb3 = list_blocks(k_force_sym_lower<DIRECT, KERN>, caches[2], a.n);
+    hipLaunchKernelGGL((k_force_sym_lower<DIRECT, KERN>), dim3((unsigned)nb3), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_sym(const PairArgs& a, int direct, int kern, hipStream_t s)
+{
+    if (direct) {
+        if (kern == SPHV_KERNEL_QUARTIC) {
+            static std::atomic<int> c[3];
+            return run_force_sym<true, SPHV_KERNEL_QUARTIC>(c, a, s);
+        }
+        static std::atomic<int> c[3];
+        return run_force_sym<true, SPHV_KERNEL_CUBIC>(c, a, s);
+    }
+    if (kern == SPHV_KERNEL_QUARTIC) {
+        static std::atomic<int> c[3];
+        return run_force_sym<false, SPHV_KERNEL_QUARTIC>(c, a, s);
+    }
+    static std::atomic<int> c[3];
+    return run_force_sym<false, SPHV_KERNEL_CUBIC>(c, a, s);
 }
 
 hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kern, hipStream_t s)

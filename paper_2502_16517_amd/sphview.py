@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libsphview.so")
 
 OK, E_INVALID_ARG, E_DESCRIPTOR, E_WORKSPACE, E_ALIAS, E_STATE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F_NONFINITE_INPUT, F_H_NOT_CONVERGED, F_H_CAP_HIT, F_QUEUE_OVERFLOW = 1, 2, 4, 8
-F_NONFINITE_OUTPUT, F_GRID_TOO_SMALL, F_OUT_OF_BOX = 16, 32, 64
+F_NONFINITE_OUTPUT, F_GRID_TOO_SMALL, F_OUT_OF_BOX, F_LIST_MISMATCH = 16, 32, 64, 128
 F64, F32, I64, I32 = 1, 2, 3, 4
 IN, OUT, INOUT = 1, 2, 3
 LAYOUT_SOA, LAYOUT_AOSOA, LAYOUT_DIRECT, LAYOUT_SORTED = 0, 1, 2, 3
@@ -62,7 +62,7 @@ class Params(C.Structure):
                 ("inv_cell", C.c_double * 3), ("grid", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
                 ("gamma", C.c_double), ("eta", C.c_double), ("cfl", C.c_double), ("h_tol", C.c_double),
                 ("headroom", C.c_double), ("max_iter", C.c_int32), ("kernel", C.c_int32),
-                ("list_cap", C.c_int32), ("reserved", C.c_int32)]
+                ("list_cap", C.c_int32), ("symmetric", C.c_int32)]
 
 
 class State(C.Structure):
