@@ -683,28 +683,35 @@ __global__ void k_force_prep(PairArgs a)
     fc[4 * a.n + p] = H * H;
 }
 
-template <bool DIRECT, bool FP32, int KERN>
-__global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
-{
+// The force list walk runs in three launches, each holding only the registers
+// of its own part, so that more waves share a SIMD and hide the latency of the
+// per-lane gathers:
+//  k_force_list_build   every particle's pairs (r < 2 max(h_i, h_j), r > 0) in
+//                       window order into its list, and their number; the pair
+//                       counts (coincident neighbours included); a list too
+//                       short for its pairs raises a flag;
+//  k_force_list_eval    the particles whose pairs fit their list: the pairs
+//                       from the list;
+//  k_force_list_window  only when the flag is up, the other particles: the
+//                       same pairs in the same order from their window.
+
+// Particle i of a force list walk: its position in the frame of the pair
+// differences and the window's culling bounds.
+template <bool DIRECT, bool FP32>
+struct ForceListPos {
     using R = typename std::conditional<FP32, float, double>::type;
-    const int lane = threadIdx.x;
-    const int64_t n = a.n;
-    const int cap = a.list_cap;
-    const R* fc = (const R*)a.fconst;
-    unsigned long long n_pairs = 0;
-    uint32_t flags = 0;
+    Loc<DIRECT> li;
+    int kx, ky, kz;
+    int r[3];
+    R xi, yi, zi, Hi, H2i;
+    double bx, by, bz;
 
-    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
-        const int64_t p = base + lane;
-        if (p >= n) continue;
+    __device__ __forceinline__ void load(const PairArgs& a, int64_t p, uint32_t& flags)
+    {
         const int cell = a.key_sorted[p];
-        int kx, ky, kz;
         cell_coords(cell, a.g, kx, ky, kz);
-        int r[3];
         lane_reach(a.g, a.reach[cell], r, flags);
-
-        const Loc<DIRECT> li = locate<DIRECT>(a.acc, p);
-        R xi, yi, zi;
+        li = locate<DIRECT>(a.acc, p);
         if constexpr (FP32) {
             xi = ld_rel(a.f[SPHV_X], li, a.g, 0, kx);
             yi = ld_rel(a.f[SPHV_Y], li, a.g, 1, ky);
@@ -714,127 +721,116 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
             yi = ld_f64(a.f[SPHV_Y], li);
             zi = ld_f64(a.f[SPHV_Z], li);
         }
-        const R vxi = ld_r<R>(a.f[SPHV_VX], li), vyi = ld_r<R>(a.f[SPHV_VY], li), vzi = ld_r<R>(a.f[SPHV_VZ], li);
-        const R hi = ld_r<R>(a.f[SPHV_H], li), rhoi = ld_r<R>(a.f[SPHV_RHO], li);
-        const R hali = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], li);
-        const R Ai = fc[p], ci = fc[n + p], hinvi = fc[2 * n + p], normi = fc[3 * n + p];
-        const R Hi = (R)2 * hi;
-        const R H2i = Hi * Hi;
-        // block culling: runs within reach of max(2 h_i, the run's largest 2h)
-        const double bx = box_pos<FP32>(xi, a.g, 0, kx), by = box_pos<FP32>(yi, a.g, 1, ky),
-                     bz = box_pos<FP32>(zi, a.g, 2, kz);
+        Hi = (R)2 * ld_r<R>(a.f[SPHV_H], li);
+        H2i = Hi * Hi;
+        bx = box_pos<FP32>(xi, a.g, 0, kx);
+        by = box_pos<FP32>(yi, a.g, 1, ky);
+        bz = box_pos<FP32>(zi, a.g, 2, kz);
+    }
+
+    // every candidate of the window that can be a pair, in window order: the
+    // runs and cells within reach of max(2 h_i, their largest 2h)
+    template <class Visit>
+    __device__ __forceinline__ void walk(const PairArgs& a, Visit&& visit) const
+    {
         const double mrg = FP32 ? a.g.cmin * 0x1p-18 : 0.0;
         auto keep = [&](const double* bnd, double sx, double sy, double sz) {
             const double rr = fmax((double)Hi, bnd[6]) * (1.0 + 1e-6) + mrg;
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rr * rr;
         };
-        // a cell is within reach of max(2 h_i, its largest 2h); a row within
-        // reach of max(2 h_i, any cell's reach)
         const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
         auto keep_cell = [&](double d2, int key) {
             const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
             const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
             return d2 < rr * rr;
         };
+        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
+    }
 
-        // ---- build: the pairs r < 2 max(h_i, h_j) (and coincident j != i), in window order
-        int32_t* L = a.list + p;
-        int len = 0;
-        int coinc = 0;   // coincident neighbours: counted as pairs, no force
-        auto pair_test = [&](int j, int jx, int jy, int jz, int ox, int oy, int oz, R& dx, R& dy, R& dz, R& r2,
-                             Loc<DIRECT>& lj) {
-            Pos<DIRECT, FP32> c;
-            lj = locate<DIRECT>(a.acc, j);
-            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-            else c.load(a, lj, jx, jy, jz);
-            r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
-            return r2 < fmax(H2i, fc[4 * n + j]);
-        };
-        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox, int oy,
-                                                                        int oz) {
-            R dx, dy, dz, r2;
-            Loc<DIRECT> lj;
-            if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj)) {
-                if (r2 > (R)0) {
-                    if (len < cap) L[(int64_t)len * n] = j;
-                    ++len;
-                } else if (j != (int)p) {
-                    ++coinc;
-                }
-            }
-        });
+    // candidate j placed in i's frame; true when (i, j) is a pair or j coincides with i
+    __device__ __forceinline__ bool pair_test(const PairArgs& a, int j, int jx, int jy, int jz, int ox, int oy,
+                                              int oz, R& dx, R& dy, R& dz, R& r2, Loc<DIRECT>& lj) const
+    {
+        const R* fc = (const R*)a.fconst;
+        Pos<DIRECT, FP32> c;
+        lj = locate<DIRECT>(a.acc, j);
+        if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+        else c.load(a, lj, jx, jy, jz);
+        r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+        return r2 < fmax(H2i, fc[4 * a.n + j]);
+    }
+};
 
-        double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0;
-        float fax = 0.f, cax = 0.f, fay = 0.f, cay = 0.f, faz = 0.f, caz = 0.f, fdu = 0.f, cdu = 0.f;
-        R pax = 0, pay = 0, paz = 0, pdu = 0;
-        int kf = 0;
-        R vsig = (R)2 * ci;
-        // one pair's contribution (r > 0)
-        auto term = [&](int j, const Loc<DIRECT>& lj, R dx, R dy, R dz, R r2) {
-            const R vxj = ld_r<R>(a.f[SPHV_VX], lj), vyj = ld_r<R>(a.f[SPHV_VY], lj), vzj = ld_r<R>(a.f[SPHV_VZ], lj);
-            const R mj = ld_r<R>(a.f[SPHV_M], lj), rhoj = ld_r<R>(a.f[SPHV_RHO], lj);
-            const R halj = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], lj);
-            const R Aj = fc[j], cj = fc[n + j], hinvj = fc[2 * n + j], normj = fc[3 * n + j];
-            const R y = rsq_l(r2);
-            const R rr = r2 * y;
-            const R gi = spl_dw<KERN>(rr * hinvi) * normi;
-            const R gj = spl_dw<KERN>(rr * hinvj) * normj;
-            const R gbar = (R)0.5 * (gi + gj);
-            const R ex = dx * y, ey = dy * y, ez = dz * y;
-            const R w = (vxi - vxj) * ex + (vyi - vyj) * ey + (vzi - vzj) * ez;
-            const R mu = w < (R)0 ? w : (R)0;
-            const R vs = ci + cj - (R)3 * mu;
-            // Pi = -(alpha_bar / 2) v_sig mu / rho_bar = -alpha_bar v_sig mu / (rho_i + rho_j)
-            const R visc = -(hali + halj) * vs * mu * rcp_l(rhoi + rhoj);
-            const R Agi = Ai * gi;
-            const R coef = mj * fma(visc, gbar, fma(Aj, gj, Agi));
-            const R dui = mj * fma((R)0.5 * visc, gbar, Agi) * w;
-            pax = fma(-coef, ex, pax);
-            pay = fma(-coef, ey, pay);
-            paz = fma(-coef, ez, paz);
-            pdu = pdu + dui;
-            vsig = vs > vsig ? vs : vsig;
-            if constexpr (FP32) {
-                if (++kf == 16) {
-                    neumaier_l(fax, cax, pax);
-                    neumaier_l(fay, cay, pay);
-                    neumaier_l(faz, caz, paz);
-                    neumaier_l(fdu, cdu, pdu);
-                    pax = pay = paz = pdu = 0;
-                    kf = 0;
-                }
-            }
-        };
+// The sums of particle i over its pairs, in the order the pairs are added.
+template <bool DIRECT, bool FP32, int KERN>
+struct ForceListSums {
+    using R = typename std::conditional<FP32, float, double>::type;
+    R vxi, vyi, vzi, rhoi, hali, Ai, ci, hinvi, normi;
+    float fax = 0.f, cax = 0.f, fay = 0.f, cay = 0.f, faz = 0.f, caz = 0.f, fdu = 0.f, cdu = 0.f;
+    R pax = 0, pay = 0, paz = 0, pdu = 0;
+    int kf = 0;
+    R vsig;
 
-        if (len <= cap) {
-            int jn = len > 0 ? L[0] : 0;
-            for (int e = 0; e < len; ++e) {
-                const int j = jn;
-                if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
-                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                Pos<DIRECT, FP32> c;
-                if constexpr (FP32) {
-                    int jx, jy, jz;
-                    cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
-                    c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1),
-                           mi_cell(jz, kz, a.g, 2));
-                } else {
-                    c.load(a, lj, 0, 0, 0);
-                }
-                R dx, dy, dz;
-                const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
-                term(j, lj, dx, dy, dz, r2);
+    __device__ __forceinline__ void load(const PairArgs& a, int64_t p, const Loc<DIRECT>& li)
+    {
+        const R* fc = (const R*)a.fconst;
+        const int64_t n = a.n;
+        vxi = ld_r<R>(a.f[SPHV_VX], li);
+        vyi = ld_r<R>(a.f[SPHV_VY], li);
+        vzi = ld_r<R>(a.f[SPHV_VZ], li);
+        rhoi = ld_r<R>(a.f[SPHV_RHO], li);
+        hali = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], li);
+        Ai = fc[p];
+        ci = fc[n + p];
+        hinvi = fc[2 * n + p];
+        normi = fc[3 * n + p];
+        vsig = (R)2 * ci;
+    }
+
+    // one pair's contribution (r > 0)
+    __device__ __forceinline__ void term(const PairArgs& a, int j, const Loc<DIRECT>& lj, R dx, R dy, R dz, R r2)
+    {
+        const R* fc = (const R*)a.fconst;
+        const int64_t n = a.n;
+        const R vxj = ld_r<R>(a.f[SPHV_VX], lj), vyj = ld_r<R>(a.f[SPHV_VY], lj), vzj = ld_r<R>(a.f[SPHV_VZ], lj);
+        const R mj = ld_r<R>(a.f[SPHV_M], lj), rhoj = ld_r<R>(a.f[SPHV_RHO], lj);
+        const R halj = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], lj);
+        const R Aj = fc[j], cj = fc[n + j], hinvj = fc[2 * n + j], normj = fc[3 * n + j];
+        const R y = rsq_l(r2);
+        const R rr = r2 * y;
+        const R gi = spl_dw<KERN>(rr * hinvi) * normi;
+        const R gj = spl_dw<KERN>(rr * hinvj) * normj;
+        const R gbar = (R)0.5 * (gi + gj);
+        const R ex = dx * y, ey = dy * y, ez = dz * y;
+        const R w = (vxi - vxj) * ex + (vyi - vyj) * ey + (vzi - vzj) * ez;
+        const R mu = w < (R)0 ? w : (R)0;
+        const R vs = ci + cj - (R)3 * mu;
+        // Pi = -(alpha_bar / 2) v_sig mu / rho_bar = -alpha_bar v_sig mu / (rho_i + rho_j)
+        const R visc = -(hali + halj) * vs * mu * rcp_l(rhoi + rhoj);
+        const R Agi = Ai * gi;
+        const R coef = mj * fma(visc, gbar, fma(Aj, gj, Agi));
+        const R dui = mj * fma((R)0.5 * visc, gbar, Agi) * w;
+        pax = fma(-coef, ex, pax);
+        pay = fma(-coef, ey, pay);
+        paz = fma(-coef, ez, paz);
+        pdu = pdu + dui;
+        vsig = vs > vsig ? vs : vsig;
+        if constexpr (FP32) {
+            if (++kf == 16) {
+                neumaier_l(fax, cax, pax);
+                neumaier_l(fay, cay, pay);
+                neumaier_l(faz, caz, paz);
+                neumaier_l(fdu, cdu, pdu);
+                pax = pay = paz = pdu = 0;
+                kf = 0;
             }
-        } else {
-            // more pairs than the list holds: the same pairs in the same order, from the window
-            walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox,
-                                                                            int oy, int oz) {
-                R dx, dy, dz, r2;
-                Loc<DIRECT> lj;
-                if (pair_test(j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj) && r2 > (R)0)
-                    term(j, lj, dx, dy, dz, r2);
-            });
         }
+    }
+
+    // the outputs of particle i
+    __device__ __forceinline__ void store(const PairArgs& a, const Loc<DIRECT>& li, uint32_t& flags)
+    {
+        double ax, ay, az, du;
         if constexpr (FP32) {
             neumaier_l(fax, cax, pax);
             neumaier_l(fay, cay, pay);
@@ -855,10 +851,45 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
         st_f64(a.f[SPHV_AZ], li, az);
         st_f64(a.f[SPHV_UDT], li, du);
         st_f64(a.f[SPHV_VSIG], li, (double)vsig);
-        n_pairs += (unsigned long long)(len + coinc);
         if (!(isfinite(ax) && isfinite(ay) && isfinite(az) && isfinite(du))) flags |= SPHV_F_NONFINITE_OUTPUT;
     }
+};
 
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_list_build(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    unsigned long long n_pairs = 0;
+    uint32_t flags = 0;
+    bool over = false;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        ForceListPos<DIRECT, FP32> I;
+        I.load(a, p, flags);
+        int32_t* L = a.list + p;
+        int len = 0;
+        int coinc = 0;   // coincident neighbours: counted as pairs, no force
+        I.walk(a, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+            R dx, dy, dz, r2;
+            Loc<DIRECT> lj;
+            if (I.pair_test(a, j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj)) {
+                if (r2 > (R)0) {
+                    if (len < cap) L[(int64_t)len * n] = j;
+                    ++len;
+                } else if (j != (int)p) {
+                    ++coinc;
+                }
+            }
+        });
+        a.list_len[p] = len;
+        over |= len > cap;
+        n_pairs += (unsigned long long)(len + coinc);
+    }
+    if (__any(over) && lane == 0) atomicOr((unsigned int*)&a.meta[META_LIST_OVF], 1u);
     for (int off = 32; off > 0; off >>= 1) {
         n_pairs += __shfl_xor(n_pairs, off, kWave);
         flags |= __shfl_xor(flags, off, kWave);
@@ -870,6 +901,88 @@ __global__ __launch_bounds__(kWave) void k_force_list(PairArgs a)
         pp[2] = 0;
         pp[3] = flags;
     }
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_list_eval(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        const int len = a.list_len[p];
+        if (len > cap) continue;
+        const Loc<DIRECT> li = locate<DIRECT>(a.acc, p);
+        int kx = 0, ky = 0, kz = 0;
+        R xi, yi, zi;
+        if constexpr (FP32) {
+            cell_coords(a.key_sorted[p], a.g, kx, ky, kz);
+            xi = ld_rel(a.f[SPHV_X], li, a.g, 0, kx);
+            yi = ld_rel(a.f[SPHV_Y], li, a.g, 1, ky);
+            zi = ld_rel(a.f[SPHV_Z], li, a.g, 2, kz);
+        } else {
+            xi = ld_f64(a.f[SPHV_X], li);
+            yi = ld_f64(a.f[SPHV_Y], li);
+            zi = ld_f64(a.f[SPHV_Z], li);
+        }
+        ForceListSums<DIRECT, FP32, KERN> S;
+        S.load(a, p, li);
+        const int32_t* L = a.list + p;
+        int jn = len > 0 ? L[0] : 0;
+        for (int e = 0; e < len; ++e) {
+            const int j = jn;
+            if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
+            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+            Pos<DIRECT, FP32> c;
+            if constexpr (FP32) {
+                int jx, jy, jz;
+                cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
+                c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1), mi_cell(jz, kz, a.g, 2));
+            } else {
+                c.load(a, lj, 0, 0, 0);
+            }
+            R dx, dy, dz;
+            const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
+            S.term(a, j, lj, dx, dy, dz, r2);
+        }
+        S.store(a, li, flags);
+    }
+    for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
+    if (lane == 0 && flags) atomicOr(&a.state->flags, flags);
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_force_list_window(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    if (a.meta[META_LIST_OVF] == 0) return;
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        if (a.list_len[p] <= cap) continue;
+        ForceListPos<DIRECT, FP32> I;
+        uint32_t unused = 0;
+        I.load(a, p, unused);
+        ForceListSums<DIRECT, FP32, KERN> S;
+        S.load(a, p, I.li);
+        I.walk(a, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+            R dx, dy, dz, r2;
+            Loc<DIRECT> lj;
+            if (I.pair_test(a, j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj) && r2 > (R)0)
+                S.term(a, j, lj, dx, dy, dz, r2);
+        });
+        S.store(a, I.li, flags);
+    }
+    for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
+    if (lane == 0 && flags) atomicOr(&a.state->flags, flags);
 }
 
 // ======================================================= symmetric force
@@ -1006,7 +1119,7 @@ __global__ __launch_bounds__(kWave) void k_force_sym_build(PairArgs a)
         over |= len > cap;
         n_pairs += (unsigned long long)(len + coinc);
     }
-    if (__any(over) && lane == 0) atomicOr((unsigned int*)&a.meta[META_SYM_OVF], 1u);
+    if (__any(over) && lane == 0) atomicOr((unsigned int*)&a.meta[META_LIST_OVF], 1u);
     for (int off = 32; off > 0; off >>= 1) {
         n_pairs += __shfl_xor(n_pairs, off, kWave);
         flags |= __shfl_xor(flags, off, kWave);
@@ -1026,7 +1139,7 @@ __global__ __launch_bounds__(kWave) void k_force_sym_upper(PairArgs a)
     const int lane = threadIdx.x;
     const int64_t n = a.n;
     const int64_t cn = (int64_t)a.list_cap * n;
-    if (a.meta[META_SYM_OVF]) return;
+    if (a.meta[META_LIST_OVF]) return;
     uint32_t flags = 0;
     for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
         const int64_t p = base + lane;
@@ -1092,7 +1205,7 @@ __global__ __launch_bounds__(kWave) void k_force_sym_lower(PairArgs a)
     const int lane = threadIdx.x;
     const int64_t n = a.n;
     const int64_t cn = (int64_t)a.list_cap * n;
-    const bool twice = a.meta[META_SYM_OVF] != 0;
+    const bool twice = a.meta[META_LIST_OVF] != 0;
     const double* fc = (const double*)a.fconst;
     uint32_t flags = 0;
     for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
@@ -1250,7 +1363,7 @@ template <bool DIRECT, int KERN>
 static hipError_t run_force_sym(std::atomic<int>* caches, const PairArgs& a0, hipStream_t s)
 {
     PairArgs a = a0;
-    hipError_t e = launch_fill_u32(a.meta + META_SYM_OVF, 0u, 1, s);
+    hipError_t e = launch_fill_u32(a.meta + META_LIST_OVF, 0u, 1, s);
     if (e != hipSuccess) return e;
     a.nblocks = list_blocks(k_force_sym_build<DIRECT, KERN>, caches[0], a.n);
     hipLaunchKernelGGL((k_force_sym_build<DIRECT, KERN>), dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
@@ -1282,14 +1395,42 @@ hipError_t launch_force_sym(const PairArgs& a, int direct, int kern, hipStream_t
     return run_force_sym<false, SPHV_KERNEL_CUBIC>(c, a, s);
 }
 
+template <bool DIRECT, bool FP32, int KERN>
+static hipError_t run_force_list(std::atomic<int>* caches, const PairArgs& a0, hipStream_t s)
+{
+    PairArgs a = a0;
+    hipError_t e = launch_fill_u32(a.meta + META_LIST_OVF, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    a.nblocks = list_blocks(k_force_list_build<DIRECT, FP32, KERN>, caches[0], a.n);
+    hipLaunchKernelGGL((k_force_list_build<DIRECT, FP32, KERN>), dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_pair_fold(a, a.nblocks, 0, s)) != hipSuccess) return e;
+    const int nb2 = list_blocks(k_force_list_eval<DIRECT, FP32, KERN>, caches[1], a.n);
+    hipLaunchKernelGGL((k_force_list_eval<DIRECT, FP32, KERN>), dim3((unsigned)nb2), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nb3 = list_blocks(k_force_list_window<DIRECT, FP32, KERN>, caches[2], a.n);
+    hipLaunchKernelGGL((k_force_list_window<DIRECT, FP32, KERN>), dim3((unsigned)nb3), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+#define SPHV_FORCE_LIST_CASE(D, F)                                                          \
+    do {                                                                                    \
+        if (kern == SPHV_KERNEL_QUARTIC) {                                                  \
+            static std::atomic<int> cq[3];                                                  \
+            return run_force_list<D, F, SPHV_KERNEL_QUARTIC>(cq, a, s);                     \
+        }                                                                                   \
+        static std::atomic<int> cc[3];                                                      \
+        return run_force_list<D, F, SPHV_KERNEL_CUBIC>(cc, a, s);                           \
+    } while (0)
+
 hipError_t launch_force_list(const PairArgs& a, int direct, int fp32, int kern, hipStream_t s)
 {
     if (direct) {
-        if (fp32) SPHV_LIST_CASE(k_force_list, true, true, 0);
-        SPHV_LIST_CASE(k_force_list, true, false, 0);
+        if (fp32) SPHV_FORCE_LIST_CASE(true, true);
+        SPHV_FORCE_LIST_CASE(true, false);
     }
-    if (fp32) SPHV_LIST_CASE(k_force_list, false, true, 0);
-    SPHV_LIST_CASE(k_force_list, false, false, 0);
+    if (fp32) SPHV_FORCE_LIST_CASE(false, true);
+    SPHV_FORCE_LIST_CASE(false, false);
 }
 
 }  // namespace sphv
