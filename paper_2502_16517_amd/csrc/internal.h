@@ -20,7 +20,7 @@ constexpr int kMaxPairBlocks = 256 * 20;   // largest grid of a pair loop
 constexpr int kPartSlots = 4;    // per-wave counters a pair loop leaves for its fold
 constexpr int kDense = 64;       // cells of more particles are ordered by sub-cell inside
 constexpr int kSubBits = 4;      // sub-cells per cell edge: 2^kSubBits
-constexpr int kBlock = 64;       // sorted positions per bounding block of the list walks
+constexpr int kBlock = 16;       // sorted positions per bounding block of the list walks (divides 64)
 constexpr int kBlockWords = 8;   // per block: lo x y z, hi x y z, largest 2h, spare
 
 // Device state block (mirrors sphv_state field for field).

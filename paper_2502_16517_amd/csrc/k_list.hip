@@ -245,7 +245,9 @@ __device__ __forceinline__ R diff(const PairArgs& a, R xi, R yi, R zi, const P& 
 template <bool DIRECT, bool FP32>
 __global__ __launch_bounds__(kWave) void k_block_bounds(PairArgs a, double* out)
 {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // one wave covers kWave / kBlock runs, each reduced over its own kBlock lanes
+    static_assert(kWave % kBlock == 0, "runs tile a wave");
+    const int64_t p = (int64_t)blockIdx.x * kWave + threadIdx.x;
     const bool valid = p < a.n;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, H = 0.0;
     if (valid) {
@@ -270,15 +272,15 @@ __global__ __launch_bounds__(kWave) void k_block_bounds(PairArgs a, double* out)
         }
         H = 2.0 * (FP32 ? (double)ld_f32v(a.f[SPHV_H], l) : ld_f64(a.f[SPHV_H], l));
     }
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
         for (int d = 0; d < 3; ++d) {
             lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, kWave));
             hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, kWave));
         }
         H = fmax(H, __shfl_xor(H, off, kWave));
     }
-    if (threadIdx.x == 0) {
-        double* o = out + (int64_t)blockIdx.x * kBlockWords;
+    if (valid && threadIdx.x % kBlock == 0) {
+        double* o = out + (p / kBlock) * kBlockWords;
         for (int d = 0; d < 3; ++d) {
             o[d] = lo[d];
             o[3 + d] = hi[d];
@@ -1334,7 +1336,7 @@ hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kern
 hipError_t launch_block_bounds(const PairArgs& a, double* blocks, int direct, int fp32, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((a.n + kBlock - 1) / kBlock);
+    const unsigned nb = (unsigned)((a.n + kWave - 1) / kWave);
     if (direct) {
         if (fp32) hipLaunchKernelGGL((k_block_bounds<true, true>), dim3(nb), dim3(kWave), 0, s, a, blocks);
         else hipLaunchKernelGGL((k_block_bounds<true, false>), dim3(nb), dim3(kWave), 0, s, a, blocks);
