@@ -285,6 +285,26 @@ def run_timed(torch, sv, st, steps, warmup, graph=False):
     return res
 
 
+def run_whole_steps(torch, st, steps, warmup):
+    """Warm up, then time exactly `steps` calls of the stepper's own step (its
+    forms that the piecewise timing does not reproduce: overlapped prefetch,
+    records reached by address); HIP events around the timed steps only."""
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        st.step()
+    torch.cuda.synchronize()
+    before = st.read_state()
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_start.record(s)
+    for _ in range(steps):
+        st.step()
+    e_end.record(s)
+    torch.cuda.synchronize()
+    after = st.read_state()
+    return dict(ms_total=e_start.elapsed_time(e_end), pairs=after.pairs_total - before.pairs_total,
+                flags=after.flags, state=after)
+
+
 def pair_evals_per_step(torch, sv, st):
     """One more (untimed) step to read the per-step pair counters."""
     st.step()
@@ -385,25 +405,64 @@ def cpu_baseline(inputs, w, kernel=0, sample_single=200_000, sample_all=1_000_00
             "single": out["single"], "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
+def scattered_records(torch, inputs, w, where, seed=5, spread=2):
+    """The records at seeded, shuffled slots of a buffer `spread` times larger,
+    in pinned host or device memory, and the device list of their addresses
+    in particle order."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    slots = rng.permutation(spread * w.n)[:w.n]
+    buf = np.zeros((spread * w.n, inputs.NSLOT), dtype=np.float64)
+    buf[slots] = w.rec
+    raw = torch.from_numpy(buf.view(np.uint8).reshape(-1))
+    raw = raw.pin_memory() if where == "host" else raw.cuda()
+    ptrs = torch.from_numpy((raw.data_ptr() + slots.astype(np.uint64) * inputs.STRIDE).astype(np.uint64)
+                            .view(np.int64)).cuda()
+    return raw, ptrs
+
+
 def host_records(torch, sv, inputs, w, desc, args):
     """The step with the records in pinned host memory: views (gathered once
     per loop) against loops on the records (every candidate fetched across
-    the host link).  One JSON line; its value is host-link inclusive."""
+    the host link); views whose force members are fetched while the density
+    loop runs; views over records scattered through a pool and reached by an
+    address list, in host and in device memory.  One JSON line; its value is
+    host-link inclusive."""
     global HOST_RECORDS
     HOST_RECORDS = True
     lays = args.layouts.split(",") if args.layouts else ["soa/tpiauto/branch", "soa/tpiauto/branch"]
     runs = {}
-    for name, names in (("views", lays), ("records", ["direct/tpiauto/branch", "direct/tpiauto/branch"])):
+    for name, names in (("views", lays), ("records", ["direct/tpiauto/branch", "direct/tpiauto/branch"]),
+                        ("views_overlap", lays), ("views_pointers_host", lays), ("views_pointers_device", lays)):
         log(f"[bench] host records, {name}: {names}")
-        st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, (tuple(w.grid), layout_of(sv, names[0]),
-                                                                layout_of(sv, names[1])))
-        r = run_timed(torch, sv, st, args.steps, args.warmup)
+        tuned = (tuple(w.grid), layout_of(sv, names[0]), layout_of(sv, names[1]))
+        if name in ("views", "records"):
+            st = make_stepper(torch, sv, inputs, w, sv.PREC_FP64, tuned)
+        else:
+            p = sv.params_init(w.lo, w.length, tuned[0], w.periodic)
+            p.eta = w.eta
+            for k, v in PKW.items():
+                setattr(p, k, v)
+            kw = dict(layout_density=tuned[1], layout_force=tuned[2], stream=torch.cuda.current_stream())
+            if name == "views_overlap":
+                import numpy as np
+                raw = torch.from_numpy(inputs.as_bytes(np.ascontiguousarray(w.rec))).pin_memory()
+                st = sv.Stepper(None, p, sv.PREC_FP64, aos=raw, overlap=True, **kw)
+            else:
+                raw, ptrs = scattered_records(torch, inputs, w, "host" if name.endswith("host") else "device")
+                st = sv.Stepper(None, p, sv.PREC_FP64, aos=raw, record_ptrs=ptrs, **kw)
+        if name in ("views", "records"):
+            r = run_timed(torch, sv, st, args.steps, args.warmup)
+            runs[name] = {"layouts": names, "ms_per_step": r["ms_total"] / args.steps,
+                          "value": r["pairs"] / (r["ms_total"] / 1e3), "ms_density": r["ms_density"],
+                          "ms_force": r["ms_force"], "ms_density_gather": r["ms_density_gather"],
+                          "ms_force_gather": r["ms_force_gather"], "ms_kick_drift": r["ms_kick_drift"],
+                          "flags": r["flags"]}
+        else:
+            r = run_whole_steps(torch, st, args.steps, args.warmup)
+            runs[name] = {"layouts": names, "ms_per_step": r["ms_total"] / args.steps,
+                          "value": r["pairs"] / (r["ms_total"] / 1e3), "flags": r["flags"]}
         st.close()
-        runs[name] = {"layouts": names, "ms_per_step": r["ms_total"] / args.steps,
-                      "value": r["pairs"] / (r["ms_total"] / 1e3), "ms_density": r["ms_density"],
-                      "ms_force": r["ms_force"], "ms_density_gather": r["ms_density_gather"],
-                      "ms_force_gather": r["ms_force_gather"], "ms_kick_drift": r["ms_kick_drift"],
-                      "flags": r["flags"]}
     out = {"metric": "pair interactions/s (density+force incl. AoS<->SoA views), records in pinned host memory",
            "value": runs["views"]["value"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": runs["views"]["ms_per_step"], "higher_is_better": True,
@@ -411,7 +470,8 @@ def host_records(torch, sv, inputs, w, desc, args):
            "config": {"workload": desc + ", 256-byte 32-slot records in pinned host memory, FP64", "n": w.n,
                       "records": "pinned host"},
            "host_records": runs,
-           "views_speedup": runs["records"]["ms_per_step"] / runs["views"]["ms_per_step"]}
+           "views_speedup": runs["records"]["ms_per_step"] / runs["views"]["ms_per_step"],
+           "overlap_speedup": runs["views"]["ms_per_step"] / runs["views_overlap"]["ms_per_step"]}
     print(json.dumps(out), flush=True)
 
 

@@ -17,16 +17,17 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _scattered(w, seed=5, spread=3):
+def _scattered(w, seed=5, spread=3, host=False):
     """The records at seeded, shuffled slots of a buffer `spread` times larger
-    (the other slots hold NaN-payload junk), and the device list of their
-    addresses in particle order."""
+    (the other slots hold NaN-payload junk), in device memory or in pinned host
+    memory, and the device list of their addresses in particle order."""
     rng = np.random.default_rng(seed)
     n = w.n
     slots = rng.permutation(spread * n)[:n]
     buf = rng.integers(0, 2**63, size=(spread * n, inputs.NSLOT), dtype=np.uint64)
     buf.view(np.float64)[slots] = w.rec
-    dev = torch.from_numpy(buf.view(np.uint8).reshape(-1).copy()).cuda()
+    raw = torch.from_numpy(buf.view(np.uint8).reshape(-1).copy())
+    dev = raw.pin_memory() if host else raw.cuda()
     ptrs = torch.from_numpy((dev.data_ptr() + slots.astype(np.uint64) * inputs.STRIDE).astype(np.uint64)
                             .view(np.int64)).cuda()
     return dev, ptrs, slots, buf
@@ -60,6 +61,27 @@ def test_pointer_records_give_contiguous_bits(orc, name, list_cap):
     # the slots the list does not name keep their junk
     others = np.setdiff1d(np.arange(full.shape[0]), slots)
     assert np.array_equal(full[others], buf[others])
+
+
+def test_pointer_records_in_pinned_host_memory(orc):
+    """Records scattered through a pool in pinned host memory, reached by a
+    device list of their addresses: three steps give the bits of the same
+    records stored contiguously on the device."""
+    w = inputs.two_state_tube(24, 31)
+    p = sv.params_for(w)
+    a = sv.Stepper(w.rec, p)
+    host, ptrs, slots, buf = _scattered(w, seed=17, host=True)
+    b = sv.Stepper(None, p, aos=host, record_ptrs=ptrs)
+    for _ in range(3):
+        a.step()
+        b.step()
+    ra, sa = a.records(), a.read_state()
+    rb, sb = b.records(), b.read_state()
+    a.close()
+    b.close()
+    assert sa.flags == sb.flags == 0
+    assert np.array_equal(bits(ra), bits(rb))
+    assert sa.dt == sb.dt and tuple(sa.sums) == tuple(sb.sums)
 
 
 def test_pointer_records_step_matches_oracle(orc):
