@@ -215,7 +215,11 @@ int32_t sphv_params_init(sphv_params* p, const double lo[3], const double len[3]
 /* ----------------------------------------------------------- state block */
 
 /* Host mirror of the device state block (sphv_state_bytes() bytes, caller-owned
- * device memory).  dt is written by sphv_step_reduce (dt_prev keeps the one
+ * device memory): what a step of the time-stepping scheme of paper Sec. 2.1
+ * carries from one step to the next (the time step size, the step count) and
+ * what it reports (error flags, conservation sums, pair counts; the paper
+ * states no error model, and reporting errors asynchronously in this block is
+ * this library's choice).  dt is written by sphv_step_reduce (dt_prev keeps the one
  * before, nstep counts its calls); sums are fixed-order FP64 totals over particles:
  *   [0..2] sum m v, [3] sum m (|v|^2/2 + u), [4..6] sum m a, [7] sum m (v.a + du/dt)
  * pairs_* count ordered pairs (i, j != i) inside the support at the accepted h
@@ -543,7 +547,12 @@ int32_t sphv_autotune_grid(void* aos_dev, const sphv_descriptor* d_density, cons
 /* ---------------------------------------------------------------- graphs */
 
 /* Capture everything enqueued on stream between begin and end into a HIP graph
- * (thread-local capture mode); launch replays it on any stream. */
+ * (thread-local capture mode); launch replays it on any stream.  A whole step
+ * becomes one launch: the answer here to the many small kernels whose launch
+ * overhead the paper's GPU measurements single out (Sec. 7.5).  Arguments: the
+ * stream (a hipStream_t, null for the default stream); out receives a handle the
+ * caller releases with sphv_graph_destroy.  Errors: SPHV_E_HIP when capture or
+ * instantiation fails, SPHV_E_INVALID_ARG for a null handle. */
 typedef struct sphv_graph sphv_graph;
 int32_t sphv_graph_begin(void* stream);
 int32_t sphv_graph_end(void* stream, sphv_graph** out);
