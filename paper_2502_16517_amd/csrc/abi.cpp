@@ -896,6 +896,10 @@ int32_t sphv_sph_density(sphv_view* v, const sphv_cells* c, const sphv_params* p
     if (c->dev.list_cap > 0) {
         a.list = c->dev.list;
         a.list_cap = c->dev.list_cap;
+        a.list_len = c->dev.list_len;
+        // the force constants' storage holds the hand-over of particles that leave
+        // their list (the force loop fills it with its constants only later)
+        a.fconst = c->dev.fconst;
         const int direct = is_direct(v->layout.kind), fp32 = v->precision == SPHV_PREC_FP32;
         if (launch_block_bounds(a, c->dev.blocks, direct, fp32, (hipStream_t)stream) != hipSuccess)
             return SPHV_E_HIP;

@@ -111,7 +111,7 @@ enum {
     META_MASKS = 2,                          // 0: no cached masks; else 1 + lanes-per-particle setting (+128 for FP32)
     META_RGLOBAL_F = 3,                      // largest own force reach
     META_SCAN = 4,                           // block tickets of the scans of cells_build (two slots)
-    META_LIST_OVF = 6,                       // force list walks: some list overflowed
+    META_LIST_OVF = 6,                       // list walks: some particle left its list (see k_list.hip)
     META_QHEAD_D = kQStride,                       // 8 per-XCD heads of the density queue, kQStride apart
     META_QHEAD_F = kQStride + kNumXcd * kQStride,  // the same for the force queue
     META_SIZE = kQStride + 2 * kNumXcd * kQStride

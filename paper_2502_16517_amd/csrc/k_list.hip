@@ -330,9 +330,12 @@ __device__ __forceinline__ int rot_offset(int t, int t0, int r)
 // bounds given, a run of kBlock sorted positions whose bounds fail
 // keep_block(bounds, sx, sy, sz), (sx, sy, sz) being the periodic shift of the
 // cell's image.
+// walk_window_runs hands visit_run(j0, j1, jx, jy, jz, ox, oy, oz) each run of
+// consecutive sorted positions [j0, j1) it keeps, in the same order.
 template <class KC, class KB, class V>
-__device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], double px,
-                                            double py, double pz, KC&& keep_cell, KB&& keep_block, V&& visit)
+__device__ __forceinline__ void walk_window_runs(const PairArgs& a, int kx, int ky, int kz, const int r[3],
+                                                 double px, double py, double pz, KC&& keep_cell, KB&& keep_block,
+                                                 V&& visit_run)
 {
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
     // offsets in the order that visits cells (so sorted positions) ascending
@@ -377,15 +380,44 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
                         const int bk = b0 / kBlock;
                         const int b1 = (bk + 1) * kBlock < je ? (bk + 1) * kBlock : je;
                         if (keep_block(a.blocks + (int64_t)bk * kBlockWords, sx, sy, sz))
-                            for (int j = b0; j < b1; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+                            visit_run(b0, b1, x2, y2, z2, dx, dy, dz);
                         b0 = b1;
                     }
-                } else {
-                    for (int j = jb; j < je; ++j) visit(j, x2, y2, z2, dx, dy, dz);
+                } else if (jb < je) {
+                    visit_run(jb, je, x2, y2, z2, dx, dy, dz);
                 }
             }
         }
     }
+}
+
+template <class KC, class KB, class V>
+__device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], double px,
+                                            double py, double pz, KC&& keep_cell, KB&& keep_block, V&& visit)
+{
+    walk_window_runs(a, kx, ky, kz, r, px, py, pz, keep_cell, keep_block,
+                     [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+                         for (int j = j0; j < j1; ++j) visit(j, jx, jy, jz, ox, oy, oz);
+                     });
+}
+
+// The candidates j0 .. j1-1 of a run, their members loaded kBatch at a time
+// (all loads of a batch issued before any is used, so that a lane has several
+// gathers in flight), then used one after the other in order.
+constexpr int kBatch = 4;
+
+template <class Load, class Use>
+__device__ __forceinline__ void batched(int j0, int j1, Load&& load, Use&& use)
+{
+    int j = j0;
+    for (; j + kBatch <= j1; j += kBatch) {
+        decltype(load(j)) v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = load(j + k);
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) use(j + k, v[k]);
+    }
+    for (; j < j1; ++j) use(j, load(j));
 }
 
 // Squared distance from (px, py, pz) minus the shift to the box of a run's bounds.
@@ -412,37 +444,43 @@ __device__ __forceinline__ double box_pos(R v, const Geom& g, int d, int k)
 
 // ================================================================ density
 
-template <bool DIRECT, bool FP32, int KERN>
-__global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
-{
-    using R = typename std::conditional<FP32, float, double>::type;
-    const int lane = threadIdx.x;
-    const int64_t n = a.n;
-    const int cap = a.list_cap;
-    const double eta3 = a.eta * a.eta * a.eta;
-    if (blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 0;   // the item kernels' mask cache is not written
-    unsigned long long n_final = 0, n_evals = 0;
-    int maxit = 0;
-    uint32_t flags = 0;
+// The density list walk runs in three launches, each holding only the
+// registers of its own part:
+//  k_density_list_build   every particle's list: the candidates of its window
+//                         within its list radius h_l = min(h_cap, (1 + 1/16) h0)
+//                         (widened diameter), in window order, and their number;
+//  k_density_list_pass    the Newton passes over the list while h stays within
+//                         h_l; a particle whose list overflowed, or whose h
+//                         leaves h_l before a pass, leaves its h, pass number and
+//                         evaluation count (in the force constants' storage,
+//                         which the force loop fills only later) for
+//  k_density_list_window  its remaining passes over the whole window (it
+//                         returns at once when no particle was left over).
+// Every particle runs the same passes in the same order as in one walk.
 
-    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
-        const int64_t p = base + lane;
-        if (p >= n) continue;
+// Particle p of the density list walk.
+template <bool DIRECT, bool FP32>
+struct DensListLane {
+    using R = typename std::conditional<FP32, float, double>::type;
+    Loc<DIRECT> li;
+    int kx, ky, kz;
+    int r[3];
+    R xi, yi, zi;
+    double mi, h0, hl, hcap;
+    R Hl2w;
+
+    __device__ __forceinline__ void load(const PairArgs& a, int64_t p, uint32_t& flags)
+    {
         const int cell = a.key_sorted[p];
-        int kx, ky, kz;
         cell_coords(cell, a.g, kx, ky, kz);
-        int r[3];
         lane_reach(a.g, a.reach[cell], r, flags);
-        double hcap = 0.5 * (double)r[0] * a.g.cell[0];
+        hcap = 0.5 * (double)r[0] * a.g.cell[0];
         hcap = fmin(hcap, 0.5 * (double)r[1] * a.g.cell[1]);
         hcap = fmin(hcap, 0.5 * (double)r[2] * a.g.cell[2]);
         // a fused r^2 is a few ulp from the exact one: the list radius is widened
         // so that it never drops a candidate the exact test would take
         constexpr double kWiden = FP32 ? 1.0 + 4e-6 : 1.0 + 1e-12;
-
-        const Loc<DIRECT> li = locate<DIRECT>(a.acc, p);
-        R xi, yi, zi;
-        double mi;
+        li = locate<DIRECT>(a.acc, p);
         if constexpr (FP32) {
             xi = ld_rel(a.f[SPHV_X], li, a.g, 0, kx);
             yi = ld_rel(a.f[SPHV_Y], li, a.g, 1, ky);
@@ -454,191 +492,132 @@ __global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
             zi = ld_f64(a.f[SPHV_Z], li);
             mi = ld_f64(a.f[SPHV_M], li);
         }
-        const double h0 = ld_f64(a.f[SPHV_H], li);
-        const double hl = fmin(hcap, kGrowL * h0);
-        const R Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
-        // block culling: the runs within reach of the radius rc
+        h0 = ld_f64(a.f[SPHV_H], li);
+        hl = fmin(hcap, kGrowL * h0);
+        Hl2w = (R)((2.0 * hl) * (2.0 * hl) * kWiden);
+    }
+
+    // the window's candidates that can lie within the cull radius 2 hh, run by
+    // run, in window order
+    template <class VisitRun>
+    __device__ __forceinline__ void walk_runs(const PairArgs& a, double hh, VisitRun&& visit_run) const
+    {
         const double bx = box_pos<FP32>(xi, a.g, 0, kx), by = box_pos<FP32>(yi, a.g, 1, ky),
                      bz = box_pos<FP32>(zi, a.g, 2, kz);
-        double rc2 = 0.0;
+        const double rr = 2.0 * hh * (1.0 + 1e-6) + (FP32 ? a.g.cmin * 0x1p-18 : 0.0);
+        const double rc2 = rr * rr;
         auto keep = [&](const double* bnd, double sx, double sy, double sz) {
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rc2;
         };
         auto keep_cell = [&](double d2, int) { return d2 < rc2; };
-        auto cull_radius = [&](double hh) {
-            const double rr = 2.0 * hh * (1.0 + 1e-6) + (FP32 ? a.g.cmin * 0x1p-18 : 0.0);
-            rc2 = rr * rr;
-        };
-        cull_radius(hl);
+        walk_window_runs(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+    }
+};
 
-        // candidate j of the window, loaded and placed in the local frame
-        auto cand = [&](int j, int jx, int jy, int jz, int ox, int oy, int oz, R& cm) {
-            Pos<DIRECT, FP32> c;
-            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-            else c.load(a, lj, jx, jy, jz);
-            cm = ld_r<R>(a.f[SPHV_M], lj);
-            return c;
-        };
+// The sums of one Newton pass at smoothing length h: sum m w, sum w and
+// sum m (3w + q w'); a candidate out of range adds the neutral element.
+template <bool FP32, int KERN>
+struct DensPassSums {
+    using R = typename std::conditional<FP32, float, double>::type;
+    R H2, hin;
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    R p0 = 0, p1 = 0, p2 = 0;
+    int kf = 0;
+    int cnt = 0;
 
-        // ---- build: the candidates within the list radius, in window order
-        int32_t* L = a.list + p;
-        int len = 0;
-        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox, int oy,
-                                                                        int oz) {
-            Pos<DIRECT, FP32> c;
-            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-            if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-            else c.load(a, lj, jx, jy, jz);
-            R dx, dy, dz;
-            if constexpr (FP32) {
-                dx = xi - c.x;
-                dy = yi - c.y;
-                dz = zi - c.z;
-            } else {
-                dx = mi_diff(xi, c.x, a.g, 0);
-                dy = mi_diff(yi, c.y, a.g, 1);
-                dz = mi_diff(zi, c.z, a.g, 2);
-            }
-            if (fma(dz, dz, fma(dy, dy, dx * dx)) < Hl2w) {
-                if (len < cap) L[(int64_t)len * n] = j;
-                ++len;
-            }
-        });
-        bool lists = len <= cap;
+    __device__ __forceinline__ explicit DensPassSums(double h)
+    {
+        H2 = (R)((2.0 * h) * (2.0 * h));
+        hin = (R)(1.0 / h);
+    }
 
-        // ---- passes of the h iteration
-        double h = h0;
-        unsigned long long it_evals = 0;
-        for (int pass = 0;; ++pass) {
-            const double hinv = 1.0 / h;
-            const R H2 = (R)((2.0 * h) * (2.0 * h));
-            const R hin = (R)hinv;
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0;       // sum m w, sum w, sum m (3w + q w')
-            float f0 = 0.f, f1 = 0.f, f2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-            R p0 = 0, p1 = 0, p2 = 0;
-            int kf = 0;
-            int cnt = 0;
-            // one candidate's contribution; out of range it is the neutral element
-            auto term = [&](R m, R r2, bool in) {
-                const R rr = r2 * rsq_l(fmax(r2, TinyL<R>::v));
-                const R q = rr * hin;
-                R w, dw;
-                spl<KERN>(q, w, dw);
-                w = in ? w : (R)0;
-                dw = in ? dw : (R)0;
-                p0 = fma(m, w, p0);
-                p1 = p1 + w;
-                p2 = fma(m, fma(q, dw, (R)3 * w), p2);
-                if constexpr (FP32) {
-                    // float partial sums folded into the compensated ones every 16 terms
-                    if (++kf == 16) {
-                        neumaier_l(f0, c0, p0);
-                        neumaier_l(f1, c1, p1);
-                        neumaier_l(f2, c2, p2);
-                        p0 = p1 = p2 = 0;
-                        kf = 0;
-                    }
-                }
-            };
-            if (lists && h <= hl) {
-                // the list walk: entry k at list[k n + p]; the next entry's index
-                // is read while the current one is evaluated
-                int jn = len > 0 ? L[0] : 0;
-                for (int e = 0; e < len; ++e) {
-                    const int j = jn;
-                    if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
-                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                    Pos<DIRECT, FP32> c;
-                    if constexpr (FP32) {
-                        int jx, jy, jz;
-                        cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
-                        c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1),
-                               mi_cell(jz, kz, a.g, 2));
-                    } else {
-                        c.load(a, lj, 0, 0, 0);
-                    }
-                    const R m = ld_r<R>(a.f[SPHV_M], lj);
-                    R dx, dy, dz;
-                    const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
-                    const bool in = r2 < H2;
-                    term(m, r2, in);
-                    cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
-                }
-            } else {
-                lists = false;
-                // the whole window: every candidate the list would hold (while h
-                // stays within h_l, those are exactly the list's entries, in its
-                // order, so the FP32 partial sums are grouped as in the list walk)
-                // and every candidate in range at the current h
-                cull_radius(fmax(hl, h));
-                walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, [&](int j, int jx, int jy, int jz, int ox,
-                                                                                int oy, int oz) {
-                    R m;
-                    const auto c = cand(j, jx, jy, jz, ox, oy, oz, m);
-                    R dx, dy, dz;
-                    const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
-                    const bool in = r2 < H2;
-                    if (in || fma(dz, dz, fma(dy, dy, dx * dx)) < Hl2w) {
-                        term(m, r2, in);
-                        cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
-                    }
-                });
-            }
-            if constexpr (FP32) {
+    __device__ __forceinline__ void term(R m, R r2, bool in)
+    {
+        const R rr = r2 * rsq_l(fmax(r2, TinyL<R>::v));
+        const R q = rr * hin;
+        R w, dw;
+        spl<KERN>(q, w, dw);
+        w = in ? w : (R)0;
+        dw = in ? dw : (R)0;
+        p0 = fma(m, w, p0);
+        p1 = p1 + w;
+        p2 = fma(m, fma(q, dw, (R)3 * w), p2);
+        if constexpr (FP32) {
+            // float partial sums folded into the compensated ones every 16 terms
+            if (++kf == 16) {
                 neumaier_l(f0, c0, p0);
                 neumaier_l(f1, c1, p1);
                 neumaier_l(f2, c2, p2);
-                t0 = (double)f0 + (double)c0;
-                t1 = (double)f1 + (double)c1;
-                t2 = (double)f2 + (double)c2;
-            } else {
-                t0 = p0;
-                t1 = p1;
-                t2 = p2;
+                p0 = p1 = p2 = 0;
+                kf = 0;
             }
-            it_evals += (unsigned long long)cnt;
-
-            const double h3 = h * h * h;
-            const double norm = 1.0 / (kPiL * h3);
-            const double rho = norm * t0;
-            const double nsum = norm * t1;
-            const double drho = -(norm * hinv) * t2;
-            const double mq = mi * eta3;
-            const double f = rho - mq / h3;
-            const double fp = drho + 3.0 * mq / (h3 * h);
-            double hn;
-            if (fp > 0.0) {
-                hn = h - f / fp;
-                if (hn < 0.5 * h) hn = 0.5 * h;
-                if (hn > 2.0 * h) hn = 2.0 * h;
-            } else {
-                hn = a.eta * cbrt(mi / rho);
-            }
-            if (!isfinite(hn)) hn = a.eta * cbrt(mi / rho);
-            if (hn > hcap) {
-                hn = hcap;
-                flags |= SPHV_F_H_CAP_HIT;
-            }
-            const bool conv = fabs(hn - h) <= a.tol * h;
-            if (conv || pass + 1 >= a.max_iter) {
-                if (!conv) flags |= SPHV_F_H_NOT_CONVERGED;
-                const double omega = 1.0 + h / (3.0 * rho) * drho;
-                const double wcount = (4.0 * kPiL / 3.0) * (8.0 * h3) * nsum;
-                if (!(isfinite(rho) && isfinite(omega))) flags |= SPHV_F_NONFINITE_OUTPUT;
-                st_f64(a.f[SPHV_H], li, h);
-                st_f64(a.f[SPHV_RHO], li, rho);
-                st_f64(a.f[SPHV_OMEGA], li, omega);
-                st_f64(a.f[SPHV_WCOUNT], li, wcount);
-                n_final += (unsigned long long)cnt;
-                maxit = pass + 1 > maxit ? pass + 1 : maxit;
-                break;
-            }
-            h = hn;
         }
-        n_evals += it_evals;
     }
 
+    __device__ __forceinline__ void totals(double& t0, double& t1, double& t2)
+    {
+        if constexpr (FP32) {
+            neumaier_l(f0, c0, p0);
+            neumaier_l(f1, c1, p1);
+            neumaier_l(f2, c2, p2);
+            t0 = (double)f0 + (double)c0;
+            t1 = (double)f1 + (double)c1;
+            t2 = (double)f2 + (double)c2;
+        } else {
+            t0 = p0;
+            t1 = p1;
+            t2 = p2;
+        }
+    }
+};
+
+// The Newton step of the h iteration after a pass at h with totals t0..t2:
+// true when the particle is done (converged, or its last pass), its outputs
+// then stored; else hn is the next h.
+template <bool DIRECT>
+__device__ __forceinline__ bool dens_newton(const PairArgs& a, const Loc<DIRECT>& li, double mi, double hcap,
+                                            double h, double t0, double t1, double t2, int pass, double& hn,
+                                            uint32_t& flags)
+{
+    const double eta3 = a.eta * a.eta * a.eta;
+    const double hinv = 1.0 / h;
+    const double h3 = h * h * h;
+    const double norm = 1.0 / (kPiL * h3);
+    const double rho = norm * t0;
+    const double nsum = norm * t1;
+    const double drho = -(norm * hinv) * t2;
+    const double mq = mi * eta3;
+    const double f = rho - mq / h3;
+    const double fp = drho + 3.0 * mq / (h3 * h);
+    if (fp > 0.0) {
+        hn = h - f / fp;
+        if (hn < 0.5 * h) hn = 0.5 * h;
+        if (hn > 2.0 * h) hn = 2.0 * h;
+    } else {
+        hn = a.eta * cbrt(mi / rho);
+    }
+    if (!isfinite(hn)) hn = a.eta * cbrt(mi / rho);
+    if (hn > hcap) {
+        hn = hcap;
+        flags |= SPHV_F_H_CAP_HIT;
+    }
+    const bool conv = fabs(hn - h) <= a.tol * h;
+    if (!(conv || pass + 1 >= a.max_iter)) return false;
+    if (!conv) flags |= SPHV_F_H_NOT_CONVERGED;
+    const double omega = 1.0 + h / (3.0 * rho) * drho;
+    const double wcount = (4.0 * kPiL / 3.0) * (8.0 * h3) * nsum;
+    if (!(isfinite(rho) && isfinite(omega))) flags |= SPHV_F_NONFINITE_OUTPUT;
+    st_f64(a.f[SPHV_H], li, h);
+    st_f64(a.f[SPHV_RHO], li, rho);
+    st_f64(a.f[SPHV_OMEGA], li, omega);
+    st_f64(a.f[SPHV_WCOUNT], li, wcount);
+    return true;
+}
+
+// per-wave counters of a density launch into its fold slots
+__device__ __forceinline__ void dens_leave(const PairArgs& a, unsigned long long n_final, unsigned long long n_evals,
+                                           int maxit, uint32_t flags)
+{
     for (int off = 32; off > 0; off >>= 1) {
         n_final += __shfl_xor(n_final, off, kWave);
         n_evals += __shfl_xor(n_evals, off, kWave);
@@ -646,13 +625,215 @@ __global__ __launch_bounds__(kWave) void k_density_list(PairArgs a)
         maxit = o > maxit ? o : maxit;
         flags |= __shfl_xor(flags, off, kWave);
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         int64_t* pp = a.part + (int64_t)blockIdx.x * kPartSlots;
         pp[0] = (int64_t)n_final;
         pp[1] = (int64_t)n_evals;
         pp[2] = maxit;
         pp[3] = flags;
     }
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_density_list_build(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    if (blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 0;   // the item kernels' mask cache is not written
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        DensListLane<DIRECT, FP32> I;
+        I.load(a, p, flags);
+        int32_t* L = a.list + p;
+        int len = 0;
+        I.walk_runs(a, I.hl, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+            batched(
+                j0, j1,
+                [&](int j) {
+                    Pos<DIRECT, FP32> c;
+                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                    if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+                    else c.load(a, lj, jx, jy, jz);
+                    return c;
+                },
+                [&](int j, const Pos<DIRECT, FP32>& c) {
+                    R dx, dy, dz;
+                    if constexpr (FP32) {
+                        dx = I.xi - c.x;
+                        dy = I.yi - c.y;
+                        dz = I.zi - c.z;
+                    } else {
+                        dx = mi_diff(I.xi, c.x, a.g, 0);
+                        dy = mi_diff(I.yi, c.y, a.g, 1);
+                        dz = mi_diff(I.zi, c.z, a.g, 2);
+                    }
+                    if (fma(dz, dz, fma(dy, dy, dx * dx)) < I.Hl2w) {
+                        if (len < cap) L[(int64_t)len * n] = j;
+                        ++len;
+                    }
+                });
+        });
+        a.list_len[p] = len;
+    }
+    for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
+    if (lane == 0 && flags) atomicOr(&a.state->flags, flags);
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_density_list_pass(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const int cap = a.list_cap;
+    double* left_h = (double*)a.fconst;
+    unsigned long long* left_evals = (unsigned long long*)a.fconst + n;
+    int64_t* left_pass = (int64_t*)a.fconst + 2 * n;
+    unsigned long long n_final = 0, n_evals = 0;
+    int maxit = 0;
+    uint32_t flags = 0;
+    bool any_left = false;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        DensListLane<DIRECT, FP32> I;
+        I.load(a, p, flags);
+        const int len = a.list_len[p];
+        const int32_t* L = a.list + p;
+        double h = I.h0;
+        unsigned long long it_evals = 0;
+        int64_t leave_at = -1;
+        for (int pass = 0;; ++pass) {
+            if (len > cap || h > I.hl) {
+                leave_at = pass;
+                break;
+            }
+            DensPassSums<FP32, KERN> S(h);
+            // the list, two entries at a time: both neighbours' loads in flight
+            // together, the next two entries' indices read meanwhile
+            struct Cand {
+                Pos<DIRECT, FP32> c;
+                R m;
+            };
+            auto cand = [&](int j) {
+                Cand v;
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                if constexpr (FP32) {
+                    int jx, jy, jz;
+                    cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
+                    v.c.load(a, lj, jx, jy, jz, mi_cell(jx, I.kx, a.g, 0), mi_cell(jy, I.ky, a.g, 1),
+                             mi_cell(jz, I.kz, a.g, 2));
+                } else {
+                    v.c.load(a, lj, 0, 0, 0);
+                }
+                v.m = ld_r<R>(a.f[SPHV_M], lj);
+                return v;
+            };
+            auto use = [&](int j, const Cand& v) {
+                R dx, dy, dz;
+                const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, v.c, dx, dy, dz);
+                const bool in = r2 < S.H2;
+                S.term(v.m, r2, in);
+                S.cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
+            };
+            int e = 0;
+            int jn0 = len > 0 ? L[0] : 0, jn1 = len > 1 ? L[n] : 0;
+            for (; e + 2 <= len; e += 2) {
+                const int j0 = jn0, j1 = jn1;
+                if (e + 2 < len) jn0 = L[(int64_t)(e + 2) * n];
+                if (e + 3 < len) jn1 = L[(int64_t)(e + 3) * n];
+                const Cand v0 = cand(j0);
+                const Cand v1 = cand(j1);
+                use(j0, v0);
+                use(j1, v1);
+            }
+            if (e < len) use(jn0, cand(jn0));
+            double t0, t1, t2;
+            S.totals(t0, t1, t2);
+            it_evals += (unsigned long long)S.cnt;
+            double hn;
+            if (dens_newton<DIRECT>(a, I.li, I.mi, I.hcap, h, t0, t1, t2, pass, hn, flags)) {
+                n_final += (unsigned long long)S.cnt;
+                maxit = pass + 1 > maxit ? pass + 1 : maxit;
+                n_evals += it_evals;
+                break;
+            }
+            h = hn;
+        }
+        left_pass[p] = leave_at;
+        if (leave_at >= 0) {
+            left_h[p] = h;
+            left_evals[p] = it_evals;
+            any_left = true;
+        }
+    }
+    if (__any(any_left) && lane == 0) atomicOr((unsigned int*)&a.meta[META_LIST_OVF], 1u);
+    dens_leave(a, n_final, n_evals, maxit, flags);
+}
+
+template <bool DIRECT, bool FP32, int KERN>
+__global__ __launch_bounds__(kWave) void k_density_list_window(PairArgs a)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t n = a.n;
+    const double* left_h = (const double*)a.fconst;
+    const unsigned long long* left_evals = (const unsigned long long*)a.fconst + n;
+    const int64_t* left_pass = (const int64_t*)a.fconst + 2 * n;
+    const bool any = a.meta[META_LIST_OVF] != 0;
+    unsigned long long n_final = 0, n_evals = 0;
+    int maxit = 0;
+    uint32_t flags = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; any && base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t p = base + lane;
+        if (p >= n) continue;
+        const int64_t first = left_pass[p];
+        if (first < 0) continue;
+        DensListLane<DIRECT, FP32> I;
+        uint32_t unused = 0;
+        I.load(a, p, unused);
+        double h = left_h[p];
+        unsigned long long it_evals = left_evals[p];
+        for (int pass = (int)first;; ++pass) {
+            DensPassSums<FP32, KERN> S(h);
+            // the whole window: every candidate the list would hold (while h
+            // stays within h_l, those are exactly the list's entries, in its
+            // order, so the FP32 partial sums are grouped as in the list walk)
+            // and every candidate in range at the current h
+            I.walk_runs(a, fmax(I.hl, h), [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+                for (int j = j0; j < j1; ++j) {
+                    Pos<DIRECT, FP32> c;
+                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                    if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+                    else c.load(a, lj, jx, jy, jz);
+                    const R m = ld_r<R>(a.f[SPHV_M], lj);
+                    R dx, dy, dz;
+                    const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, c, dx, dy, dz);
+                    const bool in = r2 < S.H2;
+                    if (in || fma(dz, dz, fma(dy, dy, dx * dx)) < I.Hl2w) {
+                        S.term(m, r2, in);
+                        S.cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
+                    }
+                }
+            });
+            double t0, t1, t2;
+            S.totals(t0, t1, t2);
+            it_evals += (unsigned long long)S.cnt;
+            double hn;
+            if (dens_newton<DIRECT>(a, I.li, I.mi, I.hcap, h, t0, t1, t2, pass, hn, flags)) {
+                n_final += (unsigned long long)S.cnt;
+                maxit = pass + 1 > maxit ? pass + 1 : maxit;
+                n_evals += it_evals;
+                break;
+            }
+            h = hn;
+        }
+    }
+    dens_leave(a, n_final, n_evals, maxit, flags);
 }
 
 // ================================================================== force
@@ -789,15 +970,38 @@ struct ForceListSums {
         vsig = (R)2 * ci;
     }
 
-    // one pair's contribution (r > 0)
-    __device__ __forceinline__ void term(const PairArgs& a, int j, const Loc<DIRECT>& lj, R dx, R dy, R dz, R r2)
+    // the members of neighbour j a pair term reads
+    struct Nb {
+        R vxj, vyj, vzj, mj, rhoj, halj, Aj, cj, hinvj, normj;
+    };
+    __device__ __forceinline__ static Nb nb_of(const PairArgs& a, int j, const Loc<DIRECT>& lj)
     {
         const R* fc = (const R*)a.fconst;
         const int64_t n = a.n;
-        const R vxj = ld_r<R>(a.f[SPHV_VX], lj), vyj = ld_r<R>(a.f[SPHV_VY], lj), vzj = ld_r<R>(a.f[SPHV_VZ], lj);
-        const R mj = ld_r<R>(a.f[SPHV_M], lj), rhoj = ld_r<R>(a.f[SPHV_RHO], lj);
-        const R halj = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], lj);
-        const R Aj = fc[j], cj = fc[n + j], hinvj = fc[2 * n + j], normj = fc[3 * n + j];
+        Nb b;
+        b.vxj = ld_r<R>(a.f[SPHV_VX], lj);
+        b.vyj = ld_r<R>(a.f[SPHV_VY], lj);
+        b.vzj = ld_r<R>(a.f[SPHV_VZ], lj);
+        b.mj = ld_r<R>(a.f[SPHV_M], lj);
+        b.rhoj = ld_r<R>(a.f[SPHV_RHO], lj);
+        b.halj = (R)0.5 * ld_r<R>(a.f[SPHV_ALPHA], lj);
+        b.Aj = fc[j];
+        b.cj = fc[n + j];
+        b.hinvj = fc[2 * n + j];
+        b.normj = fc[3 * n + j];
+        return b;
+    }
+
+    // one pair's contribution (r > 0)
+    __device__ __forceinline__ void term(const PairArgs& a, int j, const Loc<DIRECT>& lj, R dx, R dy, R dz, R r2)
+    {
+        term_nb(nb_of(a, j, lj), dx, dy, dz, r2);
+    }
+
+    __device__ __forceinline__ void term_nb(const Nb& b, R dx, R dy, R dz, R r2)
+    {
+        const R vxj = b.vxj, vyj = b.vyj, vzj = b.vzj, mj = b.mj, rhoj = b.rhoj, halj = b.halj;
+        const R Aj = b.Aj, cj = b.cj, hinvj = b.hinvj, normj = b.normj;
         const R y = rsq_l(r2);
         const R rr = r2 * y;
         const R gi = spl_dw<KERN>(rr * hinvi) * normi;
@@ -875,6 +1079,8 @@ __global__ __launch_bounds__(kWave) void k_force_list_build(PairArgs a)
         int32_t* L = a.list + p;
         int len = 0;
         int coinc = 0;   // coincident neighbours: counted as pairs, no force
+        // one candidate at a time: batching its loads costs this kernel more in
+        // occupancy (registers) than it gains in loads in flight
         I.walk(a, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
             R dx, dy, dz, r2;
             Loc<DIRECT> lj;
@@ -931,26 +1137,47 @@ __global__ __launch_bounds__(kWave) void k_force_list_eval(PairArgs a)
             yi = ld_f64(a.f[SPHV_Y], li);
             zi = ld_f64(a.f[SPHV_Z], li);
         }
-        ForceListSums<DIRECT, FP32, KERN> S;
+        using Sums = ForceListSums<DIRECT, FP32, KERN>;
+        Sums S;
         S.load(a, p, li);
         const int32_t* L = a.list + p;
-        int jn = len > 0 ? L[0] : 0;
-        for (int e = 0; e < len; ++e) {
-            const int j = jn;
-            if (e + 1 < len) jn = L[(int64_t)(e + 1) * n];
-            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+        // a neighbour's members, loaded before they are used
+        struct Cand {
             Pos<DIRECT, FP32> c;
+            typename Sums::Nb b;
+        };
+        auto cand = [&](int j) {
+            Cand v;
+            const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
             if constexpr (FP32) {
                 int jx, jy, jz;
                 cell_coords(a.key_sorted[j], a.g, jx, jy, jz);
-                c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1), mi_cell(jz, kz, a.g, 2));
+                v.c.load(a, lj, jx, jy, jz, mi_cell(jx, kx, a.g, 0), mi_cell(jy, ky, a.g, 1), mi_cell(jz, kz, a.g, 2));
             } else {
-                c.load(a, lj, 0, 0, 0);
+                v.c.load(a, lj, 0, 0, 0);
             }
+            v.b = Sums::nb_of(a, j, lj);
+            return v;
+        };
+        auto use = [&](const Cand& v) {
             R dx, dy, dz;
-            const R r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
-            S.term(a, j, lj, dx, dy, dz, r2);
+            const R r2 = diff<FP32>(a, xi, yi, zi, v.c, dx, dy, dz);
+            S.term_nb(v.b, dx, dy, dz, r2);
+        };
+        // two entries at a time: both neighbours' loads in flight together, the
+        // next two entries' indices read meanwhile
+        int e = 0;
+        int jn0 = len > 0 ? L[0] : 0, jn1 = len > 1 ? L[n] : 0;
+        for (; e + 2 <= len; e += 2) {
+            const int j0 = jn0, j1 = jn1;
+            if (e + 2 < len) jn0 = L[(int64_t)(e + 2) * n];
+            if (e + 3 < len) jn1 = L[(int64_t)(e + 3) * n];
+            const Cand v0 = cand(j0);
+            const Cand v1 = cand(j1);
+            use(v0);
+            use(v1);
         }
+        if (e < len) use(cand(jn0));
         S.store(a, li, flags);
     }
     for (int off = 32; off > 0; off >>= 1) flags |= __shfl_xor(flags, off, kWave);
@@ -1323,14 +1550,44 @@ static hipError_t run_list(K kernel, std::atomic<int>& cache, const PairArgs& a0
         return run_list(KERNEL<D, F, SPHV_KERNEL_CUBIC>, cache, a, DENS, s);                \
     } while (0)
 
+template <bool DIRECT, bool FP32, int KERN>
+static hipError_t run_density_list(std::atomic<int>* caches, const PairArgs& a0, hipStream_t s)
+{
+    PairArgs a = a0;
+    hipError_t e = launch_fill_u32(a.meta + META_LIST_OVF, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    const int nb1 = list_blocks(k_density_list_build<DIRECT, FP32, KERN>, caches[0], a.n);
+    hipLaunchKernelGGL((k_density_list_build<DIRECT, FP32, KERN>), dim3((unsigned)nb1), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // each of the two launches that run passes leaves per-wave counters, folded after it
+    a.nblocks = list_blocks(k_density_list_pass<DIRECT, FP32, KERN>, caches[1], a.n);
+    hipLaunchKernelGGL((k_density_list_pass<DIRECT, FP32, KERN>), dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_pair_fold(a, a.nblocks, 1, s)) != hipSuccess) return e;
+    a.nblocks = list_blocks(k_density_list_window<DIRECT, FP32, KERN>, caches[2], a.n);
+    hipLaunchKernelGGL((k_density_list_window<DIRECT, FP32, KERN>), dim3((unsigned)a.nblocks), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_pair_fold(a, a.nblocks, 1, s);
+}
+
+#define SPHV_DENSITY_LIST_CASE(D, F)                                                        \
+    do {                                                                                    \
+        if (kern == SPHV_KERNEL_QUARTIC) {                                                  \
+            static std::atomic<int> cq[3];                                                  \
+            return run_density_list<D, F, SPHV_KERNEL_QUARTIC>(cq, a, s);                   \
+        }                                                                                   \
+        static std::atomic<int> cc[3];                                                      \
+        return run_density_list<D, F, SPHV_KERNEL_CUBIC>(cc, a, s);                         \
+    } while (0)
+
 hipError_t launch_density_list(const PairArgs& a, int direct, int fp32, int kern, hipStream_t s)
 {
     if (direct) {
-        if (fp32) SPHV_LIST_CASE(k_density_list, true, true, 1);
-        SPHV_LIST_CASE(k_density_list, true, false, 1);
+        if (fp32) SPHV_DENSITY_LIST_CASE(true, true);
+        SPHV_DENSITY_LIST_CASE(true, false);
     }
-    if (fp32) SPHV_LIST_CASE(k_density_list, false, true, 1);
-    SPHV_LIST_CASE(k_density_list, false, false, 1);
+    if (fp32) SPHV_DENSITY_LIST_CASE(false, true);
+    SPHV_DENSITY_LIST_CASE(false, false);
 }
 
 hipError_t launch_block_bounds(const PairArgs& a, double* blocks, int direct, int fp32, hipStream_t s)
