@@ -401,21 +401,19 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
                      });
 }
 
-// The candidates j0 .. j1-1 of a run, their members loaded kBatch at a time
-// (all loads of a batch issued before any is used, so that a lane has several
+// The candidates j0 .. j1-1 of a run, their members loaded B at a time (all
+// loads of a batch issued before any is used, so that a lane has several
 // gathers in flight), then used one after the other in order.
-constexpr int kBatch = 4;
-
-template <class Load, class Use>
+template <int B, class Load, class Use>
 __device__ __forceinline__ void batched(int j0, int j1, Load&& load, Use&& use)
 {
     int j = j0;
-    for (; j + kBatch <= j1; j += kBatch) {
-        decltype(load(j)) v[kBatch];
+    for (; j + B <= j1; j += B) {
+        decltype(load(j)) v[B];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) v[k] = load(j + k);
+        for (int k = 0; k < B; ++k) v[k] = load(j + k);
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) use(j + k, v[k]);
+        for (int k = 0; k < B; ++k) use(j + k, v[k]);
     }
     for (; j < j1; ++j) use(j, load(j));
 }
@@ -651,7 +649,7 @@ __global__ __launch_bounds__(kWave) void k_density_list_build(PairArgs a)
         int32_t* L = a.list + p;
         int len = 0;
         I.walk_runs(a, I.hl, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
-            batched(
+            batched<4>(
                 j0, j1,
                 [&](int j) {
                     Pos<DIRECT, FP32> c;
@@ -713,8 +711,6 @@ __global__ __launch_bounds__(kWave) void k_density_list_pass(PairArgs a)
                 break;
             }
             DensPassSums<FP32, KERN> S(h);
-            // the list, two entries at a time: both neighbours' loads in flight
-            // together, the next two entries' indices read meanwhile
             struct Cand {
                 Pos<DIRECT, FP32> c;
                 R m;
@@ -740,18 +736,23 @@ __global__ __launch_bounds__(kWave) void k_density_list_pass(PairArgs a)
                 S.term(v.m, r2, in);
                 S.cnt += (in && (r2 > (R)0 || j != (int)p)) ? 1 : 0;
             };
+            // the list, four entries at a time: their indices, then their
+            // neighbours' loads all in flight together, then the terms in order
             int e = 0;
-            int jn0 = len > 0 ? L[0] : 0, jn1 = len > 1 ? L[n] : 0;
-            for (; e + 2 <= len; e += 2) {
-                const int j0 = jn0, j1 = jn1;
-                if (e + 2 < len) jn0 = L[(int64_t)(e + 2) * n];
-                if (e + 3 < len) jn1 = L[(int64_t)(e + 3) * n];
-                const Cand v0 = cand(j0);
-                const Cand v1 = cand(j1);
-                use(j0, v0);
-                use(j1, v1);
+            for (; e + 4 <= len; e += 4) {
+                int jj[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) jj[k] = L[(int64_t)(e + k) * n];
+                Cand vv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) vv[k] = cand(jj[k]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) use(jj[k], vv[k]);
             }
-            if (e < len) use(jn0, cand(jn0));
+            for (; e < len; ++e) {
+                const int j = L[(int64_t)e * n];
+                use(j, cand(j));
+            }
             double t0, t1, t2;
             S.totals(t0, t1, t2);
             it_evals += (unsigned long long)S.cnt;
@@ -930,6 +931,23 @@ struct ForceListPos {
         walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
     }
 
+    template <class VisitRun>
+    __device__ __forceinline__ void walk_runs(const PairArgs& a, VisitRun&& visit_run) const
+    {
+        const double mrg = FP32 ? a.g.cmin * 0x1p-18 : 0.0;
+        auto keep = [&](const double* bnd, double sx, double sy, double sz) {
+            const double rr = fmax((double)Hi, bnd[6]) * (1.0 + 1e-6) + mrg;
+            return box_d2(bnd, bx, by, bz, sx, sy, sz) < rr * rr;
+        };
+        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        auto keep_cell = [&](double d2, int key) {
+            const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
+            const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
+            return d2 < rr * rr;
+        };
+        walk_window_runs(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+    }
+
     // candidate j placed in i's frame; true when (i, j) is a pair or j coincides with i
     __device__ __forceinline__ bool pair_test(const PairArgs& a, int j, int jx, int jy, int jz, int ox, int oy,
                                               int oz, R& dx, R& dy, R& dz, R& r2, Loc<DIRECT>& lj) const
@@ -1079,19 +1097,36 @@ __global__ __launch_bounds__(kWave) void k_force_list_build(PairArgs a)
         int32_t* L = a.list + p;
         int len = 0;
         int coinc = 0;   // coincident neighbours: counted as pairs, no force
-        // one candidate at a time: batching its loads costs this kernel more in
-        // occupancy (registers) than it gains in loads in flight
-        I.walk(a, [&](int j, int jx, int jy, int jz, int ox, int oy, int oz) {
-            R dx, dy, dz, r2;
-            Loc<DIRECT> lj;
-            if (I.pair_test(a, j, jx, jy, jz, ox, oy, oz, dx, dy, dz, r2, lj)) {
-                if (r2 > (R)0) {
-                    if (len < cap) L[(int64_t)len * n] = j;
-                    ++len;
-                } else if (j != (int)p) {
-                    ++coinc;
-                }
-            }
+        // candidates two at a time (four cost this kernel more in occupancy
+        // than they gain in loads in flight)
+        const R* fc = (const R*)a.fconst;
+        struct Cand {
+            Pos<DIRECT, FP32> c;
+            R H2;
+        };
+        I.walk_runs(a, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+            batched<2>(
+                j0, j1,
+                [&](int j) {
+                    Cand v;
+                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                    if constexpr (FP32) v.c.load(a, lj, jx, jy, jz, ox, oy, oz);
+                    else v.c.load(a, lj, jx, jy, jz);
+                    v.H2 = fc[4 * n + j];
+                    return v;
+                },
+                [&](int j, const Cand& v) {
+                    R dx, dy, dz;
+                    const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, v.c, dx, dy, dz);
+                    if (r2 < fmax(I.H2i, v.H2)) {
+                        if (r2 > (R)0) {
+                            if (len < cap) L[(int64_t)len * n] = j;
+                            ++len;
+                        } else if (j != (int)p) {
+                            ++coinc;
+                        }
+                    }
+                });
         });
         a.list_len[p] = len;
         over |= len > cap;
