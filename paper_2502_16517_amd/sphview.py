@@ -99,6 +99,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (or python -m "
                           f"paper_2502_16517_amd._build) first; there is no non-HIP fallback")
+    # torch ships its own HIP runtime under another file name: loaded first, it
+    # also serves this library (one runtime per process); loaded after this
+    # library, it would bring a second runtime, whose allocations the first
+    # cannot use
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     sig = {
         "sphv_status_string": (C.c_char_p, [C.c_int32]),
