@@ -118,6 +118,26 @@ def test_h_leaving_its_list_radius_matches_oracle(orc):
     assert state.pairs_density == int(ref["count"].sum())
 
 
+@pytest.mark.parametrize("precision", [sv.PREC_FP64, sv.PREC_FP32])
+def test_h_leaving_its_list_radius_same_bits_as_window(orc, precision):
+    """Particles whose h outgrows the list radius hand their iteration over to
+    the window walk mid-way; the window visits the list's candidates in the
+    list's order, so the result has the bits of a run in which every particle
+    walks its window from the first pass (a list too short for anyone)."""
+    w = inputs.config1()
+    w.rec[:, S["h"]] *= 0.6
+    tol = 1e-6 if precision == sv.PREC_FP32 else None
+    outs = []
+    for cap in (CAP, 1):
+        print(f"[list h leaving] cap={cap} prec={precision}", flush=True)
+        dens, out, state = run_density_force(w, precision=precision, tol=tol, list_cap=cap)
+        assert state.flags == 0, state.flags
+        outs.append((dens, out, state.pairs_density, state.pair_evals_density, state.max_iters))
+    assert np.array_equal(bits(outs[0][0]), bits(outs[1][0]))
+    assert np.array_equal(bits(outs[0][1]), bits(outs[1][1]))
+    assert outs[0][2:] == outs[1][2:]
+
+
 def test_list_quartic_matches_oracle(orc):
     w = inputs.kelvin_helmholtz(24, 9)
     dens, out, state = run_density_force(w, list_cap=CAP, kernel=sv.KERNEL_QUARTIC)
