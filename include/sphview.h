@@ -266,6 +266,10 @@ int32_t sphv_write_state(void* state_dev, const sphv_state* in, void* stream);
  * / min cell) and the Chebyshev distance of every cell whose own such reach
  * covers c, h_max(c) being the largest h of c seen by the force calls since
  * the last sphv_cells_build (so repeated force calls never narrow a window).
+ * That exact window is computed when every own reach is at most 4; otherwise
+ * the window is the cover G(c), the largest own reach among the cells whose
+ * own reach covers c (at least the exact window, and G(c) min cell bounds 2h
+ * of every force partner of c's particles).
  * Work items are (cell, first sorted position, count<=64). */
 typedef struct sphv_cells sphv_cells;
 
@@ -273,7 +277,8 @@ typedef struct {
     const int32_t* perm;        /* [n]          sorted position -> record index   */
     const int32_t* cell_start;  /* [n_cells+1]                                     */
     const int32_t* key;         /* [n]          key of record i (unsorted order)   */
-    const int32_t* reach;       /* [2*n_cells]  density reach, then the force window (set by sph_force) */
+    const int32_t* reach;       /* [3*n_cells]  density reach, then the force window and the cover G
+                                   (both set by sph_force) */
     int64_t n;
     int64_t n_cells;
     int64_t max_items;

@@ -287,6 +287,7 @@ uint64_t carve_cells(CellsDev* c, char* base, int64_t n, int64_t nc, int32_t lis
     c->reach_s = c->reach_d ? c->reach_d + 2 * nc : nullptr;
     c->tmp_a = (int32_t*)take(4 * (uint64_t)nc);
     c->tmp_b = (int32_t*)take(4 * (uint64_t)nc);
+    c->cover = (uint64_t*)take(8 * 2 * (uint64_t)nc);
     c->item_start = (int32_t*)take(4 * (uint64_t)(nc + 1));
     c->items = (int4*)take(16 * (uint64_t)max_items);
     c->item_masks = (uint64_t*)take(8ull * kMaskChunks * kWave * (uint64_t)max_items);

@@ -84,7 +84,9 @@ struct CellsDev {
                            // (directly after hmax_bits: one clear covers both)
     int32_t* reach_d;      // [nc] density reach (cells_build, from h before the density loop)
     int32_t* reach_f;      // [nc] force window radius (sph_force, from the converged h)
-    int32_t* reach_s;      // [nc] upper bound of the neighbours' own force reach (box maximum)
+    int32_t* reach_s;      // [nc] cover of the own force reach: the largest own reach among the cells
+                           // whose reach covers this one (bounds 2h / cmin of every force partner)
+    uint64_t* cover;       // [2][nc] masks of the cover's axis passes
     int32_t* tmp_a;        // [nc] scratch for the reach filter / item counts
     int32_t* tmp_b;        // [nc]
     int32_t* item_start;   // [nc + 1]
@@ -127,7 +129,7 @@ struct PairArgs {
     const int32_t* reach;      // density or force reach
     const int32_t* key_sorted; // cell of sorted position p
     const int32_t* reach_d;    // density reach (the force loop compares it with its own)
-    const int32_t* reach_s;    // force: bound of the own force reach of the cells around
+    const int32_t* reach_s;    // force: cover of the own force reach (largest own reach covering the cell)
     uint64_t* item_masks;      // cached candidate masks (see CellsDev)
     int32_t* meta;             // queue counters
     int64_t* part;             // per-wave counters, folded by the launch that follows

@@ -607,34 +607,61 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(const int32_t* nit,
     }
 }
 
-// box max of reach along one axis over +-R_global cells (wrapped or clipped)
-__global__ void k_reach_axis(const int32_t* in, int32_t* out, Geom g, int axis, const int32_t* meta, int rslot,
-                             int64_t nc, DevState* st)
+// The cover of the force reach, G(A) = max{ R(B) : d(A,B) <= R(B) } with R
+// the cells' own force reach and d the Chebyshev distance in cells: the
+// largest own reach among the cells whose reach covers A.  Every force partner
+// j of a particle of A lies in such a cell B (r < 2 h_j <= R(B) cmin and
+// r >= (d - 1) cmin give d <= R(B)), so G(A) cmin bounds 2 h_j of all of them,
+// and G(A) is at least the exact window.  Bit d of a cell's mask says that a
+// cell within distance d has R >= d ("thermometer" bits 1..R of each own
+// reach); the Chebyshev ball being a cube, the dilation is separable, one pass
+// per axis, each OR-ing the masks at offset o into bits >= |o|.  The highest
+// bit after the third pass is G.  Above kCoverBits (a global reach of more
+// than 63 cells) every cell gets R_global, a looser bound.
+constexpr int kCoverBits = 63;
+
+__device__ __forceinline__ uint64_t reach_bits(int R)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    return R <= 0 ? 0ull : (R >= kCoverBits ? ~1ull : (1ull << (R + 1)) - 2ull);
+}
+
+// PASS 0 dilates the own reaches along x, 1 the masks along y, 2 along z into G
+template <int PASS>
+__global__ void k_cover_axis(const int32_t* own, const uint64_t* in, uint64_t* out, int32_t* bound, Geom g,
+                             const int32_t* meta, int rslot, int64_t nc, DevState* st)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
-    int R = meta[rslot];
-    int n = g.n[axis];
-    if (g.periodic[axis] && 2 * R + 1 > n) {
+    const int Rg = meta[rslot];
+    if (Rg > kCoverBits) {
+        if constexpr (PASS == 2) bound[c] = Rg;
+        return;
+    }
+    int R = Rg;
+    const int n = g.n[PASS];
+    if (g.periodic[PASS] && 2 * R + 1 > n) {
         if (c == 0) set_flag(st, SPHV_F_GRID_TOO_SMALL);
         R = (n - 1) / 2;
     }
     int k[3];
     cell_coords((int)c, g, k[0], k[1], k[2]);
-    int m = 0;
+    uint64_t m = 0;
     for (int d = -R; d <= R; ++d) {
-        int kk = k[axis] + d;
-        if (g.periodic[axis]) {
-            kk = ((kk % n) + n) % n;
+        int kk = k[PASS] + d;
+        if (g.periodic[PASS]) {
+            kk = kk < 0 ? kk + n : (kk >= n ? kk - n : kk);
         } else if (kk < 0 || kk >= n) {
             continue;
         }
         int q[3] = {k[0], k[1], k[2]};
-        q[axis] = kk;
-        int v = in[cell_key(q[0], q[1], q[2], g)];
-        m = v > m ? v : m;
+        q[PASS] = kk;
+        const int key = cell_key(q[0], q[1], q[2], g);
+        const uint64_t v = PASS == 0 ? reach_bits(own[key]) : in[key];
+        const int ad = d < 0 ? -d : d;
+        m |= v & (~0ull << ad);
     }
-    out[c] = m;
+    if constexpr (PASS == 2) bound[c] = m ? 63 - __clzll((long long)m) : 0;
+    else out[c] = m;
 }
 
 // Own force reach of every cell from its largest converged h: R = ceil(2 h / min
@@ -696,9 +723,9 @@ __global__ __launch_bounds__(kOwnThreads) void k_force_own(const int32_t* cell_s
 
 // Exact force window: cell A must see every cell B whose own reach covers it,
 // R_f(A) = max(R(A), max{ d(A,B) : d(A,B) <= R(B) }) with d the Chebyshev
-// distance in cells.  sep, the box maximum of R over +-R_global, bounds it from
-// above and stands in when R_global is large or a periodic axis is short;
-// otherwise shells are scanned from the outermost (at most the bound) inward.
+// distance in cells.  sep, the cover G(A) (k_cover_axis), bounds it from above
+// and stands in when R_global is large or a periodic axis is short; otherwise
+// shells are scanned from the outermost (at most the bound) inward.
 constexpr int kExactReach = 4;
 
 __global__ void k_reach_exact(const int32_t* own_r, const int32_t* sep, int32_t* out, Geom g, const int32_t* meta,
@@ -830,13 +857,14 @@ hipError_t launch_force_reach(const CellsDev& c, const FieldRef& h, uint64_t str
     hipLaunchKernelGGL(k_force_own, dim3(nblk(c.nc, kOwnThreads)), dim3(kOwnThreads), 0, s, c.cell_start, c.hmax_f,
                        g.cmin, c.tmp_a, c.meta, (int)META_RGLOBAL_F, c.nc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // separable box maximum over +-R_global (tmp_a -> tmp_b -> reach_f -> reach_s), then the exact window
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.tmp_b, g, 0, c.meta,
+    // the cover G of the own reaches (tmp_a -> cover -> cover + nc -> reach_s), then the exact window
+    const unsigned nbc = nblk(c.nc, 256);
+    hipLaunchKernelGGL(k_cover_axis<0>, dim3(nbc), dim3(256), 0, s, c.tmp_a, nullptr, c.cover, nullptr, g, c.meta,
                        (int)META_RGLOBAL_F, c.nc, st);
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_b, c.reach_f, g, 1, c.meta,
-                       (int)META_RGLOBAL_F, c.nc, st);
-    hipLaunchKernelGGL(k_reach_axis, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.reach_f, c.reach_s, g, 2, c.meta,
-                       (int)META_RGLOBAL_F, c.nc, st);
+    hipLaunchKernelGGL(k_cover_axis<1>, dim3(nbc), dim3(256), 0, s, nullptr, c.cover, c.cover + c.nc, nullptr, g,
+                       c.meta, (int)META_RGLOBAL_F, c.nc, st);
+    hipLaunchKernelGGL(k_cover_axis<2>, dim3(nbc), dim3(256), 0, s, nullptr, c.cover + c.nc, nullptr, c.reach_s, g,
+                       c.meta, (int)META_RGLOBAL_F, c.nc, st);
     hipLaunchKernelGGL(k_reach_exact, dim3(nblk(c.nc, 256)), dim3(256), 0, s, c.tmp_a, c.reach_s, c.reach_f, g, c.meta,
                        (int)META_RGLOBAL_F, c.nc);
     return hipGetLastError();

@@ -332,7 +332,22 @@ __device__ __forceinline__ int rot_offset(int t, int t0, int r)
 // cell's image.
 // walk_window_runs hands visit_run(j0, j1, jx, jy, jz, ox, oy, oz) each run of
 // consecutive sorted positions [j0, j1) it keeps, in the same order.
-template <class KC, class KB, class V>
+//
+// With SEG (for visits that do not need the candidates' cells) the cells of a
+// row that the row's bound keeps, keep_cell(d2, -1), are consecutive in x
+// (the box distance falls, then rises, along the row) and so are their
+// candidates in sorted position: the row's kept range of cells (two pieces
+// when it wraps round a periodic x axis) is then one run, read from two cell
+// offsets instead of two per cell, whenever it holds at most kSeg candidates
+// (so no cell of it is dense).  A longer range is walked cell by cell as
+// without SEG.  The run's candidates are a superset of those the cells would
+// give (all those within the row bound), in the same order; such a run is
+// handed over with jx = -1 and ox = 0.  In sparse regions, where a window
+// spans many cells with few particles, this replaces most of the walk's
+// dependent loads.
+constexpr int kSeg = kDense;
+
+template <bool SEG, class KC, class KB, class V>
 __device__ __forceinline__ void walk_window_runs(const PairArgs& a, int kx, int ky, int kz, const int r[3],
                                                  double px, double py, double pz, KC&& keep_cell, KB&& keep_block,
                                                  V&& visit_run)
@@ -341,7 +356,6 @@ __device__ __forceinline__ void walk_window_runs(const PairArgs& a, int kx, int 
     // offsets in the order that visits cells (so sorted positions) ascending
     const int t0z = rot_start(kz, r[2], nz, a.g.periodic[2]);
     const int t0y = rot_start(ky, r[1], ny, a.g.periodic[1]);
-    const int t0x = rot_start(kx, r[0], nx, a.g.periodic[0]);
     for (int tz = 0; tz <= 2 * r[2]; ++tz) {
         const int dz = rot_offset(tz, t0z, r[2]);
         int z2 = kz + dz;
@@ -361,41 +375,108 @@ __device__ __forceinline__ void walk_window_runs(const PairArgs& a, int kx, int 
             const double dyz = fma(ey, ey, ez * ez);
             if (!keep_cell(dyz, -1)) continue;
             const int row = (z2 * ny + y2) * nx;
-            for (int tx = 0; tx <= 2 * r[0]; ++tx) {
-                const int dx = rot_offset(tx, t0x, r[0]);
-                int x2 = kx + dx;
-                if (x2 < 0 || x2 >= nx) {
-                    if (!a.g.periodic[0]) continue;
-                    x2 += x2 < 0 ? nx : -nx;
+            // the row's offsets [da, db]: the whole window row, or with SEG the
+            // offsets the row bound keeps, grown from a kept offset next to the
+            // local cell (the one holding the particle, at distance 0) or found
+            // by a scan of the window row
+            int da = -r[0], db = r[0];
+            if constexpr (SEG) {
+                auto row_keeps = [&](int dx) {
+                    const double ex = slab_dist(px, kx + dx, a.g, 0);
+                    return keep_cell(fma(ex, ex, dyz), -1);
+                };
+                int d0 = 0;
+                bool found = row_keeps(0);
+                if (!found && r[0] >= 1) {
+                    if (row_keeps(-1)) d0 = -1, found = true;
+                    else if (row_keeps(1)) d0 = 1, found = true;
                 }
-                const double ex = slab_dist(px, kx + dx, a.g, 0);
-                if (!keep_cell(fma(ex, ex, dyz), row + x2)) continue;
-                const int jb = a.cell_start[row + x2];
-                const int je = a.cell_start[row + x2 + 1];
-                if (a.blocks && je - jb > kDense) {
-                    const double sx = kx + dx - x2 > 0 ? a.g.len[0] : (kx + dx - x2 < 0 ? -a.g.len[0] : 0.0);
-                    const double sy = ky + dy - y2 > 0 ? a.g.len[1] : (ky + dy - y2 < 0 ? -a.g.len[1] : 0.0);
-                    const double sz = kz + dz - z2 > 0 ? a.g.len[2] : (kz + dz - z2 < 0 ? -a.g.len[2] : 0.0);
-                    for (int b0 = jb; b0 < je;) {
-                        const int bk = b0 / kBlock;
-                        const int b1 = (bk + 1) * kBlock < je ? (bk + 1) * kBlock : je;
-                        if (keep_block(a.blocks + (int64_t)bk * kBlockWords, sx, sy, sz))
-                            visit_run(b0, b1, x2, y2, z2, dx, dy, dz);
-                        b0 = b1;
+                if (found) {
+                    da = db = d0;
+                    while (da > -r[0] && row_keeps(da - 1)) --da;
+                    while (db < r[0] && row_keeps(db + 1)) ++db;
+                } else {
+                    int lo_k = r[0] + 1, hi_k = -r[0] - 1;
+                    for (int dx = -r[0]; dx <= r[0]; ++dx)
+                        if (row_keeps(dx)) {
+                            lo_k = dx < lo_k ? dx : lo_k;
+                            hi_k = dx;
+                        }
+                    if (lo_k > hi_k) continue;
+                    da = lo_k;
+                    db = hi_k;
+                }
+            }
+            // those cells in unwrapped x, in at most two pieces of ascending
+            // wrapped index, each with its shift s = unwrapped - wrapped
+            int ua = kx + da, ub = kx + db;
+            if (!a.g.periodic[0]) {
+                ua = ua < 0 ? 0 : ua;
+                ub = ub > nx - 1 ? nx - 1 : ub;
+                if (ua > ub) continue;
+            }
+            int a0 = ua, b0 = ub, s0 = 0, a1 = 0, b1 = -1, s1 = 0;
+            if (ub < 0) {
+                a0 = ua + nx, b0 = ub + nx, s0 = -nx;
+            } else if (ua >= nx) {
+                a0 = ua - nx, b0 = ub - nx, s0 = nx;
+            } else if (ua < 0) {
+                a0 = 0, b0 = ub;
+                a1 = ua + nx, b1 = nx - 1, s1 = -nx;
+            } else if (ub >= nx) {
+                a0 = 0, b0 = ub - nx, s0 = nx;
+                a1 = ua, b1 = nx - 1;
+            }
+            for (int q = 0; q < 2; ++q) {
+                const int xa = q ? a1 : a0, xb = q ? b1 : b0, sq = q ? s1 : s0;
+                if (xa > xb) break;
+                // with SEG, a piece of at most kSeg candidates is one run
+                bool whole = false;
+                int wb = 0, we = 0;
+                if constexpr (SEG) {
+                    wb = a.cell_start[row + xa];
+                    we = a.cell_start[row + xb + 1];
+                    whole = we - wb <= kSeg;
+                }
+                for (int x2 = xa; x2 <= xb; ++x2) {
+                    const int dx = x2 + sq - kx;
+                    int jb = wb, je = we;
+                    bool dense = false;
+                    if (!whole) {
+                        const double ex = slab_dist(px, kx + dx, a.g, 0);
+                        if (!keep_cell(fma(ex, ex, dyz), row + x2)) continue;
+                        jb = a.cell_start[row + x2];
+                        je = a.cell_start[row + x2 + 1];
+                        dense = a.blocks && je - jb > kDense;
                     }
-                } else if (jb < je) {
-                    visit_run(jb, je, x2, y2, z2, dx, dy, dz);
+                    // the cell's runs of kBlock sorted positions when dense, else
+                    // the cell (or the whole piece) as one run
+                    for (int j0 = jb; j0 < je;) {
+                        int j1 = je;
+                        bool keep = true;
+                        if (dense) {
+                            const int bk = j0 / kBlock;
+                            j1 = (bk + 1) * kBlock < je ? (bk + 1) * kBlock : je;
+                            const double sx = sq > 0 ? a.g.len[0] : (sq < 0 ? -a.g.len[0] : 0.0);
+                            const double sy = ky + dy - y2 > 0 ? a.g.len[1] : (ky + dy - y2 < 0 ? -a.g.len[1] : 0.0);
+                            const double sz = kz + dz - z2 > 0 ? a.g.len[2] : (kz + dz - z2 < 0 ? -a.g.len[2] : 0.0);
+                            keep = keep_block(a.blocks + (int64_t)bk * kBlockWords, sx, sy, sz);
+                        }
+                        if (keep) visit_run(j0, j1, whole ? -1 : x2, y2, z2, whole ? 0 : dx, dy, dz);
+                        j0 = j1;
+                    }
+                    if (whole) break;
                 }
             }
         }
     }
 }
 
-template <class KC, class KB, class V>
+template <bool SEG, class KC, class KB, class V>
 __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, int kz, const int r[3], double px,
                                             double py, double pz, KC&& keep_cell, KB&& keep_block, V&& visit)
 {
-    walk_window_runs(a, kx, ky, kz, r, px, py, pz, keep_cell, keep_block,
+    walk_window_runs<SEG>(a, kx, ky, kz, r, px, py, pz, keep_cell, keep_block,
                      [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
                          for (int j = j0; j < j1; ++j) visit(j, jx, jy, jz, ox, oy, oz);
                      });
@@ -508,7 +589,7 @@ struct DensListLane {
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rc2;
         };
         auto keep_cell = [&](double d2, int) { return d2 < rc2; };
-        walk_window_runs(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+        walk_window_runs<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
     }
 };
 
@@ -922,13 +1003,15 @@ struct ForceListPos {
             const double rr = fmax((double)Hi, bnd[6]) * (1.0 + 1e-6) + mrg;
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rr * rr;
         };
-        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        // a row is kept within the largest 2h any force partner of the cell's
+        // particles can have (the cover of the own force reaches)
+        const double Hg = (double)a.reach_s[cell_key(kx, ky, kz, a.g)] * a.g.cmin;
         auto keep_cell = [&](double d2, int key) {
             const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
             const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
             return d2 < rr * rr;
         };
-        walk_window(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
+        walk_window<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
     }
 
     template <class VisitRun>
@@ -939,13 +1022,15 @@ struct ForceListPos {
             const double rr = fmax((double)Hi, bnd[6]) * (1.0 + 1e-6) + mrg;
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rr * rr;
         };
-        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        // a row is kept within the largest 2h any force partner of the cell's
+        // particles can have (the cover of the own force reaches)
+        const double Hg = (double)a.reach_s[cell_key(kx, ky, kz, a.g)] * a.g.cmin;
         auto keep_cell = [&](double d2, int key) {
             const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
             const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
             return d2 < rr * rr;
         };
-        walk_window_runs(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+        walk_window_runs<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
     }
 
     // candidate j placed in i's frame; true when (i, j) is a pair or j coincides with i
@@ -1355,7 +1440,9 @@ __global__ __launch_bounds__(kWave) void k_force_sym_build(PairArgs a)
             const double rr = fmax(L.Hi, bnd[6]) * (1.0 + 1e-6);
             return box_d2(bnd, L.bx, L.by, L.bz, sx, sy, sz) < rr * rr;
         };
-        const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+        // a row is kept within the largest 2h any force partner of the cell's
+        // particles can have (the cover of the own force reaches)
+        const double Hg = (double)a.reach_s[cell_key(L.kx, L.ky, L.kz, a.g)] * a.g.cmin;
         auto keep_cell = [&](double d2, int key) {
             const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
             const double rr = fmax(L.Hi, Hc) * (1.0 + 1e-6);
@@ -1363,7 +1450,7 @@ __global__ __launch_bounds__(kWave) void k_force_sym_build(PairArgs a)
         };
         int32_t* Ls = a.list + p;
         int len = 0, coinc = 0;
-        walk_window(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
+        walk_window<true>(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
                     [&](int j, int, int, int, int, int, int) {
                         const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
                         const double dx = mi_diff(L.xi, ld_f64(a.f[SPHV_X], lj), a.g, 0);
@@ -1503,7 +1590,9 @@ __global__ __launch_bounds__(kWave) void k_force_sym_lower(PairArgs a)
                 const double rr = fmax(L.Hi, bnd[6]) * (1.0 + 1e-6);
                 return box_d2(bnd, L.bx, L.by, L.bz, sx, sy, sz) < rr * rr;
             };
-            const double Hg = (double)a.meta[META_RGLOBAL_F] * a.g.cmin;
+            // a row is kept within the largest 2h any force partner of the cell's
+            // particles can have (the cover of the own force reaches)
+            const double Hg = (double)a.reach_s[cell_key(L.kx, L.ky, L.kz, a.g)] * a.g.cmin;
             auto keep_cell = [&](double d2, int key) {
                 const double Hc = key < 0 ? Hg : (double)__uint_as_float(a.cell_h[key]);
                 const double rr = fmax(L.Hi, Hc) * (1.0 + 1e-6);
@@ -1511,7 +1600,7 @@ __global__ __launch_bounds__(kWave) void k_force_sym_lower(PairArgs a)
             };
             ax = ay = az = du = 0.0;
             vsig = 2.0 * L.ci;
-            walk_window(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
+            walk_window<true>(a, L.kx, L.ky, L.kz, L.r, L.bx, L.by, L.bz, keep_cell, keep,
                         [&](int j, int, int, int, int, int, int) {
                             const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
                             const double dx = mi_diff(L.xi, ld_f64(a.f[SPHV_X], lj), a.g, 0);

@@ -1046,8 +1046,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         axis_reach(a, Rf, gx, r);
         // the density loop cached the candidates within twice its cell cap for
         // this window; they hold every force pair when the windows agree and no
-        // cell around has a larger own force reach (no neighbour's support
-        // reaches further than the cap)
+        // cell whose reach covers these has a larger own force reach (no
+        // partner's support reaches further than the cap)
         const bool reuse = !MASKED && masks_tag == 1 + a.tpi + (FP32 ? 128 : 0) && Rf == Rd && Rs <= Rd;
         int n_spans = 0, W = 0;
         const bool use_spans = build_spans(a, kx, ky, kz, gx, r, lane, spans, n_spans, W);

@@ -758,7 +758,9 @@ class Stepper:
         return self.aos.cpu().numpy().view(np.float64).reshape(self.n, inputs.NSLOT).copy()
 
     def cells_arrays(self):
-        """perm, cell_start, key (host copies) of the last cells_build."""
+        """perm, cell_start, key and the reach arrays (density reach, force
+        window, cover of the force reach; host copies) of the last cells_build
+        and force call."""
         import torch
         info = cells_get_info(self.cells)
         nc = info.n_cells
@@ -771,7 +773,7 @@ class Stepper:
 
         torch.cuda.synchronize()
         return (view_i32(info.perm, self.n), view_i32(info.cell_start, nc + 1), view_i32(info.key, self.n),
-                view_i32(info.reach, 2 * nc))
+                view_i32(info.reach, 3 * nc))
 
     def _destroy_views(self):
         vd, vf = getattr(self, "v_dens", None), getattr(self, "v_force", None)

@@ -51,11 +51,14 @@ def test_cells_build_exact(orc, name):
 
 def _window_model(w, own):
     """Exact force window: R_f(A) = max(R(A), max{d : a cell B at Chebyshev
-    distance d has own reach R(B) >= d})."""
+    distance d has own reach R(B) >= d}); and the cover G(A) = max{R(B) : B at
+    Chebyshev distance d <= R(B)}, the largest own reach among the cells whose
+    reach covers A."""
     g = tuple(int(v) for v in w.grid)
     R = own.reshape(g[2], g[1], g[0])
     Rg = int(R.max())
     out = R.copy()
+    cover = R.copy()
     for dz in range(-Rg, Rg + 1):
         for dy in range(-Rg, Rg + 1):
             for dx in range(-Rg, Rg + 1):
@@ -71,7 +74,21 @@ def _window_model(w, own):
                         shape[ax] = -1
                         valid &= ((idx >= 0) & (idx < R.shape[ax])).reshape(shape)
                 out = np.maximum(out, np.where(valid & (sh >= d), d, 0))
-    return out.ravel(), Rg
+                cover = np.maximum(cover, np.where(valid & (sh >= d), sh, 0))
+    return out.ravel(), Rg, cover.ravel()
+
+
+def _own_force_reach(h, start, nc, cmin):
+    own = np.zeros(nc, dtype=np.int64)
+    for c in range(nc):
+        if start[c + 1] > start[c]:
+            # 2 h of the cell's largest h rounded up to float, as the kernel folds it
+            H = 2.0 * h[start[c]:start[c + 1]].max()
+            f = np.float32(H)
+            if float(f) < H:
+                f = np.nextafter(f, np.float32(np.inf))
+            own[c] = max(1, int(np.ceil(float(f) * (1.0 + 1e-12) / cmin)))
+    return own
 
 
 @pytest.mark.parametrize("steps", [1, 6])
@@ -89,21 +106,44 @@ def test_force_window_is_exact(orc, steps):
     st.close()
     nc = w.grid[0] * w.grid[1] * w.grid[2]
     rf = reach[nc:2 * nc]
+    rs = reach[2 * nc:3 * nc]
     h = rec[perm, S["h"]]
     cmin = min(p.cell[0], p.cell[1], p.cell[2])
-    own = np.zeros(nc, dtype=np.int64)
-    for c in range(nc):
-        if start[c + 1] > start[c]:
-            # 2 h of the cell's largest h rounded up to float, as the kernel folds it
-            H = 2.0 * h[start[c]:start[c + 1]].max()
-            f = np.float32(H)
-            if float(f) < H:
-                f = np.nextafter(f, np.float32(np.inf))
-            own[c] = max(1, int(np.ceil(float(f) * (1.0 + 1e-12) / cmin)))
-    exact, Rg = _window_model(w, own)
+    own = _own_force_reach(h, start, nc, cmin)
+    exact, Rg, cover = _window_model(w, own)
     assert (rf >= exact).all()
+    if all(2 * Rg + 1 <= n for n in w.grid):
+        assert np.array_equal(rs, cover)
     if Rg <= 4 and all(2 * Rg + 1 <= n for n in w.grid):
         assert np.array_equal(rf, exact)
+
+
+def test_force_window_cover_open_box(orc):
+    """A Plummer sphere in an open box, cells of 0.05: the halo's h spans many
+    cells (global reach above 4), so every cell's window is the cover G, the
+    largest own reach among the cells whose reach covers it."""
+    w = inputs.plummer(65536, 5, cell=0.05)
+    st = _stepper(w)
+    for _ in range(2):
+        st.step()
+    perm, start, _, reach = st.cells_arrays()
+    rec = st.records()
+    p = st.p
+    st.close()
+    nc = w.grid[0] * w.grid[1] * w.grid[2]
+    rf = reach[nc:2 * nc]
+    rs = reach[2 * nc:3 * nc]
+    h = rec[perm, S["h"]]
+    own = _own_force_reach(h, start, nc, min(p.cell[0], p.cell[1], p.cell[2]))
+    exact, Rg, cover = _window_model(w, own)
+    assert Rg > 4
+    assert np.array_equal(rs, cover)
+    assert np.array_equal(rf, cover)
+    assert (cover >= exact).all()
+    # the particles' windows stay well inside +-R_global (the core's cells are
+    # covered only by their neighbours' small reaches)
+    key = np.repeat(np.arange(nc), np.diff(start))
+    assert cover[key].mean() < 0.5 * Rg
 
 
 def test_cells_flags_nonfinite(orc):
