@@ -342,9 +342,10 @@ __device__ __forceinline__ int rot_offset(int t, int t0, int r)
 // (so no cell of it is dense).  A longer range is walked cell by cell as
 // without SEG.  The run's candidates are a superset of those the cells would
 // give (all those within the row bound), in the same order; such a run is
-// handed over with jx = -1 and ox = 0.  In sparse regions, where a window
-// spans many cells with few particles, this replaces most of the walk's
-// dependent loads.
+// handed over with jx = -1 and ox the window offset of the row's cell 0
+// (run_cell gives each candidate's cell and offset).  In sparse regions,
+// where a window spans many cells with few particles, this replaces most of
+// the walk's dependent loads.
 constexpr int kSeg = kDense;
 
 template <bool SEG, class KC, class KB, class V>
@@ -462,7 +463,7 @@ __device__ __forceinline__ void walk_window_runs(const PairArgs& a, int kx, int 
                             const double sz = kz + dz - z2 > 0 ? a.g.len[2] : (kz + dz - z2 < 0 ? -a.g.len[2] : 0.0);
                             keep = keep_block(a.blocks + (int64_t)bk * kBlockWords, sx, sy, sz);
                         }
-                        if (keep) visit_run(j0, j1, whole ? -1 : x2, y2, z2, whole ? 0 : dx, dy, dz);
+                        if (keep) visit_run(j0, j1, whole ? -1 : x2, y2, z2, whole ? sq - kx : dx, dy, dz);
                         j0 = j1;
                     }
                     if (whole) break;
@@ -480,6 +481,16 @@ __device__ __forceinline__ void walk_window(const PairArgs& a, int kx, int ky, i
                      [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
                          for (int j = j0; j < j1; ++j) visit(j, jx, jy, jz, ox, oy, oz);
                      });
+}
+
+// Candidate j of a run handed over by walk_window_runs: its cell x index jx
+// and window offset ox, read from its key when the run spans several cells of
+// its row (jx < 0, ox the offset of the row's cell 0).
+__device__ __forceinline__ void run_cell(const PairArgs& a, int j, int jy, int jz, int& jx, int& ox)
+{
+    if (jx >= 0) return;
+    jx = a.key_sorted[j] - (jz * a.g.n[1] + jy) * a.g.n[0];
+    ox += jx;
 }
 
 // The candidates j0 .. j1-1 of a run, their members loaded B at a time (all
@@ -589,7 +600,7 @@ struct DensListLane {
             return box_d2(bnd, bx, by, bz, sx, sy, sz) < rc2;
         };
         auto keep_cell = [&](double d2, int) { return d2 < rc2; };
-        walk_window_runs<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+        walk_window_runs<true>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
     }
 };
 
@@ -735,8 +746,13 @@ __global__ __launch_bounds__(kWave) void k_density_list_build(PairArgs a)
                 [&](int j) {
                     Pos<DIRECT, FP32> c;
                     const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                    if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-                    else c.load(a, lj, jx, jy, jz);
+                    if constexpr (FP32) {
+                        int cx = jx, co = ox;
+                        run_cell(a, j, jy, jz, cx, co);
+                        c.load(a, lj, cx, jy, jz, co, oy, oz);
+                    } else {
+                        c.load(a, lj, jx, jy, jz);
+                    }
                     return c;
                 },
                 [&](int j, const Pos<DIRECT, FP32>& c) {
@@ -890,8 +906,13 @@ __global__ __launch_bounds__(kWave) void k_density_list_window(PairArgs a)
                 for (int j = j0; j < j1; ++j) {
                     Pos<DIRECT, FP32> c;
                     const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                    if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-                    else c.load(a, lj, jx, jy, jz);
+                    if constexpr (FP32) {
+                        int cx = jx, co = ox;
+                        run_cell(a, j, jy, jz, cx, co);
+                        c.load(a, lj, cx, jy, jz, co, oy, oz);
+                    } else {
+                        c.load(a, lj, jx, jy, jz);
+                    }
                     const R m = ld_r<R>(a.f[SPHV_M], lj);
                     R dx, dy, dz;
                     const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, c, dx, dy, dz);
@@ -1011,7 +1032,7 @@ struct ForceListPos {
             const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
             return d2 < rr * rr;
         };
-        walk_window<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
+        walk_window<true>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit);
     }
 
     template <class VisitRun>
@@ -1030,7 +1051,7 @@ struct ForceListPos {
             const double rr = fmax((double)Hi, Hc) * (1.0 + 1e-6) + mrg;
             return d2 < rr * rr;
         };
-        walk_window_runs<!FP32>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
+        walk_window_runs<true>(a, kx, ky, kz, r, bx, by, bz, keep_cell, keep, visit_run);
     }
 
     // candidate j placed in i's frame; true when (i, j) is a pair or j coincides with i
@@ -1040,8 +1061,13 @@ struct ForceListPos {
         const R* fc = (const R*)a.fconst;
         Pos<DIRECT, FP32> c;
         lj = locate<DIRECT>(a.acc, j);
-        if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
-        else c.load(a, lj, jx, jy, jz);
+        if constexpr (FP32) {
+            int cx = jx, co = ox;
+            run_cell(a, j, jy, jz, cx, co);
+            c.load(a, lj, cx, jy, jz, co, oy, oz);
+        } else {
+            c.load(a, lj, jx, jy, jz);
+        }
         r2 = diff<FP32>(a, xi, yi, zi, c, dx, dy, dz);
         return r2 < fmax(H2i, fc[4 * a.n + j]);
     }
@@ -1195,8 +1221,13 @@ __global__ __launch_bounds__(kWave) void k_force_list_build(PairArgs a)
                 [&](int j) {
                     Cand v;
                     const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                    if constexpr (FP32) v.c.load(a, lj, jx, jy, jz, ox, oy, oz);
-                    else v.c.load(a, lj, jx, jy, jz);
+                    if constexpr (FP32) {
+                        int cx = jx, co = ox;
+                        run_cell(a, j, jy, jz, cx, co);
+                        v.c.load(a, lj, cx, jy, jz, co, oy, oz);
+                    } else {
+                        v.c.load(a, lj, jx, jy, jz);
+                    }
                     v.H2 = fc[4 * n + j];
                     return v;
                 },
