@@ -356,7 +356,8 @@ enum { SPHV_PREC_FP64 = 0, SPHV_PREC_FP32 = 1 };
  * them instead of testing every candidate again. */
 typedef struct {
     uint32_t kind;
-    uint32_t aosoa_width;   /* power of two, 8..1024, for SPHV_LAYOUT_AOSOA */
+    uint32_t aosoa_width;   /* power of two, 1..1024, for SPHV_LAYOUT_AOSOA (1: each */
+                            /* particle's view members packed together)          */
     uint32_t tpi;
     uint32_t masked;
 } sphv_layout;

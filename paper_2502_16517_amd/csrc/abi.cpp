@@ -371,7 +371,7 @@ int32_t check_layout(const sphv_layout* l, int32_t precision)
 {
     if (!l) return SPHV_E_INVALID_ARG;
     if (l->kind > SPHV_LAYOUT_SORTED) return SPHV_E_INVALID_ARG;
-    if (l->kind == SPHV_LAYOUT_AOSOA && (!is_pow2(l->aosoa_width) || l->aosoa_width < 8 || l->aosoa_width > 1024))
+    if (l->kind == SPHV_LAYOUT_AOSOA && (!is_pow2(l->aosoa_width) || l->aosoa_width < 1 || l->aosoa_width > 1024))
         return SPHV_E_INVALID_ARG;
     if (l->tpi > 64) return SPHV_E_INVALID_ARG;
     if (l->masked > 1) return SPHV_E_INVALID_ARG;

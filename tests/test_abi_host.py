@@ -143,8 +143,12 @@ def test_workspace_sizes():
     assert f >= 1000 * 8 * 8
     # 8 members x 8 B per element at least
     assert a >= 1000 * 64
-    # AoSoA width must be a power of two in [8, 1024]
+    # AoSoA width must be a power of two in [1, 1024]
     assert sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 12), sv.PREC_FP64) == 0
+    assert sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 0), sv.PREC_FP64) == 0
+    assert sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 2048), sv.PREC_FP64) == 0
+    # width 1: each element's 8 members packed in one 64-byte block
+    assert sv.view_workspace_bytes(d, 1000, sv.layout(sv.LAYOUT_AOSOA, 1), sv.PREC_FP64) >= 1000 * 64
     p = sv.params_init((0, 0, 0), (1, 1, 1), (6, 6, 6), (1, 1, 1))
     assert sv.cells_workspace_bytes(4096, p) > 4096 * 16 + 216 * 4
 

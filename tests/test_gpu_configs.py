@@ -91,6 +91,7 @@ def test_list_walk_full_size_sampled_parity(orc, name):
 
 TUBE_LAYOUTS = {
     "soa": sv.layout(sv.LAYOUT_SOA),
+    "aosoa1": sv.layout(sv.LAYOUT_AOSOA, 1),
     "aosoa8": sv.layout(sv.LAYOUT_AOSOA, 8),
     "direct": sv.layout(sv.LAYOUT_DIRECT),
     "sorted": sv.layout(sv.LAYOUT_SORTED),

@@ -61,6 +61,7 @@ def test_list_force_fp64_matches_oracle(orc, name):
 
 LAYOUTS = {
     "soa": sv.layout(sv.LAYOUT_SOA),
+    "aosoa1": sv.layout(sv.LAYOUT_AOSOA, 1),
     "aosoa8": sv.layout(sv.LAYOUT_AOSOA, 8),
     "aosoa64": sv.layout(sv.LAYOUT_AOSOA, 64),
     "direct": sv.layout(sv.LAYOUT_DIRECT),
