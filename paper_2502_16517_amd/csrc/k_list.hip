@@ -532,6 +532,219 @@ __device__ __forceinline__ double box_pos(R v, const Geom& g, int d, int k)
     else return v;
 }
 
+// ------------------------------------------------------- coherent waves
+//
+// The 64 lanes of a list build are 64 consecutive sorted positions.  When they
+// all lie in one dense cell (the core of a clustered distribution), each
+// lane's own walk keeps a slightly different set of runs, and the wave pays
+// for the union of them with one gather per candidate and lane.  Such a wave
+// instead walks its shared window once: a row, cell or run of kBlock positions
+// is kept when it can lie within reach of the lanes' bounding box (never
+// closer than any lane, with the largest of their radii: a superset of every
+// lane's own culling), its candidates are staged into LDS 64 at a time by the
+// whole wave (one gather per candidate), and every lane tests every staged
+// candidate in order.  A lane's hits are those of its own walk, in the same
+// order.  (A wave that straddles two dense cells holds the last sub-cells of
+// one, its far corner in sub-cell order, and the first of the next, its near
+// corner: its box spans the cells' whole y and z extent, and walking the union
+// of its lanes' windows together cost more than their own walks.)
+
+struct WaveBox {
+    double lo[3], hi[3];
+};
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// The lanes' box-frame positions spanned (every lane active).
+__device__ __forceinline__ WaveBox wave_box(double bx, double by, double bz)
+{
+    WaveBox w;
+    const double b[3] = {bx, by, bz};
+    for (int d = 0; d < 3; ++d) {
+        w.lo[d] = wave_min_d(b[d]);
+        w.hi[d] = wave_max_d(b[d]);
+    }
+    return w;
+}
+
+// A wave of the list builds is coherent when its 64 positions are particles of
+// one cell of more than kDense particles (with run bounds built).
+__device__ __forceinline__ bool wave_coherent(const PairArgs& a, int64_t p)
+{
+    const bool active = p < a.n;
+    const int cell = active ? a.key_sorted[p] : -1;
+    const int c0 = __builtin_amdgcn_readfirstlane(cell);
+    if (!a.blocks || !__all(active && cell == c0)) return false;
+    return a.cell_start[c0 + 1] - a.cell_start[c0] > kDense;
+}
+
+// Distance from the wave box's interval along axis d to the slab of cell k.
+__device__ __forceinline__ double slab_dist_box(const WaveBox& w, int k, const Geom& g, int d)
+{
+    const double lo = g.lo[d] + (double)k * g.cell[d];
+    return fmax(fmax(lo - w.hi[d], w.lo[d] - (lo + g.cell[d])), 0.0);
+}
+
+// Squared distance from the wave box, moved by minus the shift, to a run's bounds.
+__device__ __forceinline__ double box_box_d2(const double* bnd, const WaveBox& w, double sx, double sy, double sz)
+{
+    const double s[3] = {sx, sy, sz};
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = fmax(fmax(bnd[d] - (w.hi[d] - s[d]), (w.lo[d] - s[d]) - bnd[3 + d]), 0.0);
+        d2 = fma(e, e, d2);
+    }
+    return d2;
+}
+
+// The coherent wave's walk of the window of cell (kx, ky, kz): the same rows,
+// cells and runs as walk_window_runs, in the same order, kept by the wave box:
+// a row when its (y, z) distance is below rr_row, a cell when its distance is
+// below cell_rr(key), a run of a dense cell when its bounds' distance is below
+// run_rr(bounds) (the lanes test 64 runs at a time).  add_run(j0, j1, jx, jy,
+// jz, ox, oy, oz) takes each kept run, j1 - j0 <= kWave.
+template <class CR, class RR, class Add>
+__device__ __forceinline__ void walk_wave(const PairArgs& a, int kx, int ky, int kz, const int r[3],
+                                          const WaveBox& w, double rr_row, CR&& cell_rr, RR&& run_rr,
+                                          Add&& add_run)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    const int t0z = rot_start(kz, r[2], nz, a.g.periodic[2]);
+    const int t0y = rot_start(ky, r[1], ny, a.g.periodic[1]);
+    const int t0x = rot_start(kx, r[0], nx, a.g.periodic[0]);
+    for (int tz = 0; tz <= 2 * r[2]; ++tz) {
+        const int dz = rot_offset(tz, t0z, r[2]);
+        int z2 = kz + dz;
+        if (z2 < 0 || z2 >= nz) {
+            if (!a.g.periodic[2]) continue;
+            z2 += z2 < 0 ? nz : -nz;
+        }
+        const double ez = slab_dist_box(w, kz + dz, a.g, 2);
+        for (int ty = 0; ty <= 2 * r[1]; ++ty) {
+            const int dy = rot_offset(ty, t0y, r[1]);
+            int y2 = ky + dy;
+            if (y2 < 0 || y2 >= ny) {
+                if (!a.g.periodic[1]) continue;
+                y2 += y2 < 0 ? ny : -ny;
+            }
+            const double ey = slab_dist_box(w, ky + dy, a.g, 1);
+            const double dyz = fma(ey, ey, ez * ez);
+            if (!(dyz < rr_row * rr_row)) continue;
+            const int row = (z2 * ny + y2) * nx;
+            for (int tx = 0; tx <= 2 * r[0]; ++tx) {
+                const int dx = rot_offset(tx, t0x, r[0]);
+                int x2 = kx + dx;
+                if (x2 < 0 || x2 >= nx) {
+                    if (!a.g.periodic[0]) continue;
+                    x2 += x2 < 0 ? nx : -nx;
+                }
+                const double ex = slab_dist_box(w, kx + dx, a.g, 0);
+                const double rc = cell_rr(row + x2);
+                if (!(fma(ex, ex, dyz) < rc * rc)) continue;
+                const int jb = __builtin_amdgcn_readfirstlane(a.cell_start[row + x2]);
+                const int je = __builtin_amdgcn_readfirstlane(a.cell_start[row + x2 + 1]);
+                if (jb >= je) continue;
+                if (je - jb <= kDense) {
+                    add_run(jb, je, x2, y2, z2, dx, dy, dz);
+                    continue;
+                }
+                const double sx = kx + dx - x2 > 0 ? a.g.len[0] : (kx + dx - x2 < 0 ? -a.g.len[0] : 0.0);
+                const double sy = ky + dy - y2 > 0 ? a.g.len[1] : (ky + dy - y2 < 0 ? -a.g.len[1] : 0.0);
+                const double sz = kz + dz - z2 > 0 ? a.g.len[2] : (kz + dz - z2 < 0 ? -a.g.len[2] : 0.0);
+                const int bfirst = jb / kBlock, blast = (je - 1) / kBlock;
+                for (int b0 = bfirst; b0 <= blast; b0 += kWave) {
+                    const int b = b0 + lane;
+                    bool keep = false;
+                    if (b <= blast) {
+                        const double* bnd = a.blocks + (int64_t)b * kBlockWords;
+                        const double rb = run_rr(bnd);
+                        keep = box_box_d2(bnd, w, sx, sy, sz) < rb * rb;
+                    }
+                    for (uint64_t m = __ballot(keep); m; m &= m - 1) {
+                        const int bb = b0 + __builtin_ctzll(m);
+                        const int j0 = bb * kBlock > jb ? bb * kBlock : jb;
+                        const int j1 = (bb + 1) * kBlock < je ? (bb + 1) * kBlock : je;
+                        add_run(j0, j1, x2, y2, z2, dx, dy, dz);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The staging of a coherent wave's candidates: runs are appended to a chunk of
+// at most kWave candidates (their sorted positions, and for an FP32 view their
+// cell and window offset); a full chunk, and the last one, is staged by the
+// wave (stage(t, j, jx, jy, jz, ox, oy, oz) by lane t) and then taken by every
+// lane in order (use(t, j)).
+struct WaveChunk {
+    int j[kWave];
+    int key[kWave];
+    int off[kWave];
+};
+
+template <bool FP32, class Stage, class Use>
+struct WaveRuns {
+    const PairArgs& a;
+    WaveChunk& c;
+    Stage& stage;
+    Use& use;
+    int fill = 0;
+
+    __device__ __forceinline__ WaveRuns(const PairArgs& a_, WaveChunk& c_, Stage& s_, Use& u_)
+        : a(a_), c(c_), stage(s_), use(u_)
+    {
+    }
+
+    __device__ __forceinline__ void flush()
+    {
+        if (fill == 0) return;
+        const int lane = threadIdx.x & (kWave - 1);
+        __syncthreads();
+        if (lane < fill) {
+            int jx = 0, jy = 0, jz = 0, ox = 0, oy = 0, oz = 0;
+            if constexpr (FP32) {
+                cell_coords(c.key[lane], a.g, jx, jy, jz);
+                const int o = c.off[lane];
+                ox = (o & 1023) - 512;
+                oy = ((o >> 10) & 1023) - 512;
+                oz = ((o >> 20) & 1023) - 512;
+            }
+            stage(lane, c.j[lane], jx, jy, jz, ox, oy, oz);
+        }
+        __syncthreads();
+        for (int t = 0; t < fill; ++t) use(t, c.j[t]);
+        __syncthreads();
+        fill = 0;
+    }
+
+    __device__ __forceinline__ void add(int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz)
+    {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int len = j1 - j0;
+        if (fill + len > kWave) flush();
+        if (lane < len) {
+            c.j[fill + lane] = j0 + lane;
+            if constexpr (FP32) {
+                c.key[fill + lane] = (jz * a.g.n[1] + jy) * a.g.n[0] + jx;
+                c.off[fill + lane] = (ox + 512) | ((oy + 512) << 10) | ((oz + 512) << 20);
+            }
+        }
+        fill += len;
+    }
+};
+
 // ================================================================ density
 
 // The density list walk runs in three launches, each holding only the
@@ -732,13 +945,64 @@ __global__ __launch_bounds__(kWave) void k_density_list_build(PairArgs a)
     const int64_t n = a.n;
     const int cap = a.list_cap;
     if (blockIdx.x == 0 && lane == 0) a.meta[META_MASKS] = 0;   // the item kernels' mask cache is not written
+    __shared__ WaveChunk chunk;
+    __shared__ R s_x[kWave], s_y[kWave], s_z[kWave];
     uint32_t flags = 0;
     for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
         const int64_t p = base + lane;
+        auto take = [&](const DensListLane<DIRECT, FP32>& I, int j, const Pos<DIRECT, FP32>& c, int& len) {
+            R dx, dy, dz;
+            if constexpr (FP32) {
+                dx = I.xi - c.x;
+                dy = I.yi - c.y;
+                dz = I.zi - c.z;
+            } else {
+                dx = mi_diff(I.xi, c.x, a.g, 0);
+                dy = mi_diff(I.yi, c.y, a.g, 1);
+                dz = mi_diff(I.zi, c.z, a.g, 2);
+            }
+            if (fma(dz, dz, fma(dy, dy, dx * dx)) < I.Hl2w) {
+                if (len < cap) a.list[p + (int64_t)len * n] = j;
+                ++len;
+            }
+        };
+        if (wave_coherent(a, p)) {
+            // one walk for the wave, within the largest list diameter of its lanes
+            DensListLane<DIRECT, FP32> I;
+            I.load(a, p, flags);
+            const WaveBox w = wave_box(box_pos<FP32>(I.xi, a.g, 0, I.kx), box_pos<FP32>(I.yi, a.g, 1, I.ky),
+                                       box_pos<FP32>(I.zi, a.g, 2, I.kz));
+            const double rr = wave_max_d(2.0 * I.hl * (1.0 + 1e-6) + (FP32 ? a.g.cmin * 0x1p-18 : 0.0));
+            int len = 0;
+            auto stage = [&](int t, int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+                Pos<DIRECT, FP32> c;
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+                else c.load(a, lj, jx, jy, jz);
+                s_x[t] = c.x;
+                s_y[t] = c.y;
+                s_z[t] = c.z;
+            };
+            auto use = [&](int t, int j) {
+                Pos<DIRECT, FP32> c;
+                c.x = s_x[t];
+                c.y = s_y[t];
+                c.z = s_z[t];
+                take(I, j, c, len);
+            };
+            WaveRuns<FP32, decltype(stage), decltype(use)> runs(a, chunk, stage, use);
+            walk_wave(
+                a, I.kx, I.ky, I.kz, I.r, w, rr, [&](int) { return rr; }, [&](const double*) { return rr; },
+                [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+                    runs.add(j0, j1, jx, jy, jz, ox, oy, oz);
+                });
+            runs.flush();
+            a.list_len[p] = len;
+            continue;
+        }
         if (p >= n) continue;
         DensListLane<DIRECT, FP32> I;
         I.load(a, p, flags);
-        int32_t* L = a.list + p;
         int len = 0;
         I.walk_runs(a, I.hl, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
             batched<4>(
@@ -755,22 +1019,7 @@ __global__ __launch_bounds__(kWave) void k_density_list_build(PairArgs a)
                     }
                     return c;
                 },
-                [&](int j, const Pos<DIRECT, FP32>& c) {
-                    R dx, dy, dz;
-                    if constexpr (FP32) {
-                        dx = I.xi - c.x;
-                        dy = I.yi - c.y;
-                        dz = I.zi - c.z;
-                    } else {
-                        dx = mi_diff(I.xi, c.x, a.g, 0);
-                        dy = mi_diff(I.yi, c.y, a.g, 1);
-                        dz = mi_diff(I.zi, c.z, a.g, 2);
-                    }
-                    if (fma(dz, dz, fma(dy, dy, dx * dx)) < I.Hl2w) {
-                        if (len < cap) L[(int64_t)len * n] = j;
-                        ++len;
-                    }
-                });
+                [&](int j, const Pos<DIRECT, FP32>& c) { take(I, j, c, len); });
         });
         a.list_len[p] = len;
     }
@@ -1197,53 +1446,92 @@ __global__ __launch_bounds__(kWave) void k_force_list_build(PairArgs a)
     const int lane = threadIdx.x;
     const int64_t n = a.n;
     const int cap = a.list_cap;
+    __shared__ WaveChunk chunk;
+    __shared__ R s_x[kWave], s_y[kWave], s_z[kWave], s_h[kWave];
     unsigned long long n_pairs = 0;
     uint32_t flags = 0;
     bool over = false;
+    const R* fc = (const R*)a.fconst;
     for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
         const int64_t p = base + lane;
-        if (p >= n) continue;
-        ForceListPos<DIRECT, FP32> I;
-        I.load(a, p, flags);
-        int32_t* L = a.list + p;
         int len = 0;
         int coinc = 0;   // coincident neighbours: counted as pairs, no force
-        // candidates two at a time (four cost this kernel more in occupancy
-        // than they gain in loads in flight)
-        const R* fc = (const R*)a.fconst;
-        struct Cand {
-            Pos<DIRECT, FP32> c;
-            R H2;
+        auto take = [&](const ForceListPos<DIRECT, FP32>& I, int j, const Pos<DIRECT, FP32>& c, R H2j) {
+            R dx, dy, dz;
+            const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, c, dx, dy, dz);
+            if (r2 < fmax(I.H2i, H2j)) {
+                if (r2 > (R)0) {
+                    if (len < cap) a.list[p + (int64_t)len * n] = j;
+                    ++len;
+                } else if (j != (int)p) {
+                    ++coinc;
+                }
+            }
         };
-        I.walk_runs(a, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
-            batched<2>(
-                j0, j1,
-                [&](int j) {
-                    Cand v;
-                    const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
-                    if constexpr (FP32) {
-                        int cx = jx, co = ox;
-                        run_cell(a, j, jy, jz, cx, co);
-                        v.c.load(a, lj, cx, jy, jz, co, oy, oz);
-                    } else {
-                        v.c.load(a, lj, jx, jy, jz);
-                    }
-                    v.H2 = fc[4 * n + j];
-                    return v;
-                },
-                [&](int j, const Cand& v) {
-                    R dx, dy, dz;
-                    const R r2 = diff<FP32>(a, I.xi, I.yi, I.zi, v.c, dx, dy, dz);
-                    if (r2 < fmax(I.H2i, v.H2)) {
-                        if (r2 > (R)0) {
-                            if (len < cap) L[(int64_t)len * n] = j;
-                            ++len;
-                        } else if (j != (int)p) {
-                            ++coinc;
-                        }
-                    }
+        if (wave_coherent(a, p)) {
+            // one walk for the wave, within the largest support of its lanes
+            ForceListPos<DIRECT, FP32> I;
+            I.load(a, p, flags);
+            const WaveBox w = wave_box(I.bx, I.by, I.bz);
+            const double Hmax = wave_max_d((double)I.Hi);
+            const double mrg = FP32 ? a.g.cmin * 0x1p-18 : 0.0;
+            const double Hg = (double)a.reach_s[cell_key(I.kx, I.ky, I.kz, a.g)] * a.g.cmin;
+            const double rr_row = fmax(Hmax, Hg) * (1.0 + 1e-6) + mrg;
+            auto stage = [&](int t, int j, int jx, int jy, int jz, int ox, int oy, int oz) {
+                Pos<DIRECT, FP32> c;
+                const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                if constexpr (FP32) c.load(a, lj, jx, jy, jz, ox, oy, oz);
+                else c.load(a, lj, jx, jy, jz);
+                s_x[t] = c.x;
+                s_y[t] = c.y;
+                s_z[t] = c.z;
+                s_h[t] = fc[4 * n + j];
+            };
+            auto use = [&](int t, int j) {
+                Pos<DIRECT, FP32> c;
+                c.x = s_x[t];
+                c.y = s_y[t];
+                c.z = s_z[t];
+                take(I, j, c, s_h[t]);
+            };
+            WaveRuns<FP32, decltype(stage), decltype(use)> runs(a, chunk, stage, use);
+            walk_wave(
+                a, I.kx, I.ky, I.kz, I.r, w, rr_row,
+                [&](int key) { return fmax(Hmax, (double)__uint_as_float(a.cell_h[key])) * (1.0 + 1e-6) + mrg; },
+                [&](const double* bnd) { return fmax(Hmax, bnd[6]) * (1.0 + 1e-6) + mrg; },
+                [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+                    runs.add(j0, j1, jx, jy, jz, ox, oy, oz);
                 });
-        });
+            runs.flush();
+        } else {
+            if (p >= n) continue;
+            ForceListPos<DIRECT, FP32> I;
+            I.load(a, p, flags);
+            // candidates two at a time (four cost this kernel more in occupancy
+            // than they gain in loads in flight)
+            struct Cand {
+                Pos<DIRECT, FP32> c;
+                R H2;
+            };
+            I.walk_runs(a, [&](int j0, int j1, int jx, int jy, int jz, int ox, int oy, int oz) {
+                batched<2>(
+                    j0, j1,
+                    [&](int j) {
+                        Cand v;
+                        const Loc<DIRECT> lj = locate<DIRECT>(a.acc, j);
+                        if constexpr (FP32) {
+                            int cx = jx, co = ox;
+                            run_cell(a, j, jy, jz, cx, co);
+                            v.c.load(a, lj, cx, jy, jz, co, oy, oz);
+                        } else {
+                            v.c.load(a, lj, jx, jy, jz);
+                        }
+                        v.H2 = fc[4 * n + j];
+                        return v;
+                    },
+                    [&](int j, const Cand& v) { take(I, j, v.c, v.H2); });
+            });
+        }
         a.list_len[p] = len;
         over |= len > cap;
         n_pairs += (unsigned long long)(len + coinc);

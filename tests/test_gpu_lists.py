@@ -106,6 +106,26 @@ def test_short_lists_walk_the_window_bit_identical(orc, precision):
         assert (pd, pf, pe) == outs[0][2:]
 
 
+@pytest.mark.parametrize("precision", [sv.PREC_FP64, sv.PREC_FP32])
+def test_dense_cells_lists_same_bits_as_window_walks(orc, precision):
+    """A Plummer sphere whose core cells hold hundreds to thousands of
+    particles: waves whose 64 particles share one dense cell build their lists
+    from one walk of the shared window (candidates staged for the whole wave);
+    the results are those of every particle walking its own window (a list
+    capacity of one), bit for bit, with the same pair counts."""
+    w = inputs.plummer(8192, 5, cell=0.1)
+    tol = 1e-6 if precision == sv.PREC_FP32 else None
+    outs = []
+    for cap in (CAP, 1):
+        print(f"[dense lists] cap {cap} prec={precision}", flush=True)
+        dens, out, state = run_density_force(w, precision=precision, tol=tol, list_cap=cap, headroom=1.6)
+        assert state.flags & ~sv.F_OUT_OF_BOX == 0, state.flags
+        outs.append((dens, out, state.pairs_density, state.pairs_force, state.pair_evals_density))
+    assert np.array_equal(bits(outs[1][0]), bits(outs[0][0]))
+    assert np.array_equal(bits(outs[1][1]), bits(outs[0][1]))
+    assert outs[1][2:] == outs[0][2:]
+
+
 def test_h_leaving_its_list_radius_matches_oracle(orc):
     """Starting h far below its converged value: h grows past the list radius
     (1 + 1/16 of the starting h) and those particles finish on the window walk;
