@@ -14,7 +14,7 @@
 //   scan, items offsets of each cell's items, then the items (cell, first,
 //               count <= 64, cells) and n_items in the same second pass
 // and of the force window, at the start of sph_force, from the converged h:
-//   own reach per cell, separable box maximum over +-R_global, exact window.
+//   own reach per cell, its cover (three separable mask passes), exact window.
 #include "k_common.h"
 
 namespace sphv {
@@ -723,12 +723,12 @@ __global__ __launch_bounds__(kOwnThreads) void k_force_own(const int32_t* cell_s
 
 // Exact force window: cell A must see every cell B whose own reach covers it,
 // R_f(A) = max(R(A), max{ d(A,B) : d(A,B) <= R(B) }) with d the Chebyshev
-// distance in cells.  sep, the cover G(A) (k_cover_axis), bounds it from above
+// distance in cells.  The cover G(A) (k_cover_axis) bounds it from above
 // and stands in when R_global is large or a periodic axis is short; otherwise
 // shells are scanned from the outermost (at most the bound) inward.
 constexpr int kExactReach = 4;
 
-__global__ void k_reach_exact(const int32_t* own_r, const int32_t* sep, int32_t* out, Geom g, const int32_t* meta,
+__global__ void k_reach_exact(const int32_t* own_r, const int32_t* cover, int32_t* out, Geom g, const int32_t* meta,
                               int rslot, int64_t nc)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -738,14 +738,14 @@ __global__ void k_reach_exact(const int32_t* own_r, const int32_t* sep, int32_t*
     for (int d = 0; d < 3; ++d)
         if (g.periodic[d] && 2 * R + 1 > g.n[d]) exact = false;
     if (!exact) {
-        out[c] = sep[c];
+        out[c] = cover[c];
         return;
     }
     int k[3];
     cell_coords((int)c, g, k[0], k[1], k[2]);
     const int own = own_r[c];
     int best = own;
-    const int top = sep[c] < R ? sep[c] : R;
+    const int top = cover[c] < R ? cover[c] : R;
     for (int d = top; d > own && best == own; --d) {
         for (int dz = -d; dz <= d && best == own; ++dz) {
             int z = k[2] + dz;
