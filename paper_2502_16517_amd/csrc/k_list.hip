@@ -578,14 +578,15 @@ __device__ __forceinline__ WaveBox wave_box(double bx, double by, double bz)
 }
 
 // A wave of the list builds is coherent when its 64 positions are particles of
-// one cell of more than kDense particles (with run bounds built).
+// one cell of more than kDense particles (with run bounds built) whose window
+// offsets fit the staging's 10-bit fields.
 __device__ __forceinline__ bool wave_coherent(const PairArgs& a, int64_t p)
 {
     const bool active = p < a.n;
     const int cell = active ? a.key_sorted[p] : -1;
     const int c0 = __builtin_amdgcn_readfirstlane(cell);
     if (!a.blocks || !__all(active && cell == c0)) return false;
-    return a.cell_start[c0 + 1] - a.cell_start[c0] > kDense;
+    return a.cell_start[c0 + 1] - a.cell_start[c0] > kDense && a.reach[c0] < 512;
 }
 
 // Distance from the wave box's interval along axis d to the slab of cell k.
