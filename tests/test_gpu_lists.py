@@ -126,6 +126,45 @@ def test_dense_cells_lists_same_bits_as_window_walks(orc, precision):
     assert outs[1][2:] == outs[0][2:]
 
 
+def _plummer_on_a_periodic_corner():
+    """A Plummer sphere (radius 0.5) moved onto the corner of the periodic box
+    [0, 2)^3: its dense core cells sit against all three periodic faces, so
+    their windows wrap."""
+    w = inputs.plummer(8192, 5, rmax=0.5, cell=0.1)
+    rec = w.rec.copy()
+    for k in ("x", "y", "z"):
+        v = np.mod(rec[:, S[k]], 2.0)
+        rec[:, S[k]] = np.where(v >= 2.0, v - 2.0, v)
+    return inputs.Workload("plummer8k_periodic_corner", rec, (0.0, 0.0, 0.0), (2.0, 2.0, 2.0), (1, 1, 1),
+                           (20, 20, 20), w.eta)
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_FP64, sv.PREC_FP32])
+def test_dense_cells_across_periodic_faces(orc, precision):
+    """Dense cells against periodic faces: the lists built by waves that share
+    a dense cell (windows wrapping round the box) give the bits of every
+    particle walking its own window, and (FP64) match the oracle."""
+    w = _plummer_on_a_periodic_corner()
+    tol = 1e-6 if precision == sv.PREC_FP32 else None
+    outs = []
+    for cap in (CAP, 1):
+        print(f"[periodic dense lists] cap {cap} prec={precision}", flush=True)
+        dens, out, state = run_density_force(w, precision=precision, tol=tol, list_cap=cap, headroom=1.6)
+        assert state.flags == 0, state.flags
+        outs.append((dens, out, state.pairs_density, state.pairs_force, state.pair_evals_density))
+    assert np.array_equal(bits(outs[1][0]), bits(outs[0][0]))
+    assert np.array_equal(bits(outs[1][1]), bits(outs[0][1]))
+    assert outs[1][2:] == outs[0][2:]
+    if precision == sv.PREC_FP64:
+        dens, out = outs[0][0], outs[0][1]
+        ref = oracle_density(orc, w)
+        check_density(dens, ref, tol=1e-12)
+        assert outs[0][2] == int(ref["count"].sum())
+        fref = oracle_force(orc, w, dens)
+        check_force(out, fref, tol=1e-12, vsig_tol=1e-14)
+        assert outs[0][3] == int(fref["count"].sum())
+
+
 def test_h_leaving_its_list_radius_matches_oracle(orc):
     """Starting h far below its converged value: h grows past the list radius
     (1 + 1/16 of the starting h) and those particles finish on the window walk;
