@@ -3,16 +3,18 @@
 //
 // Mapping onto gfx950: one lane per local particle i (view element p = sorted
 // position), 64 consecutive particles per wave, waves over the particles in a
-// grid-stride loop.  No LDS, no barriers: every lane is independent, so the
-// kernels hold many waves per SIMD to hide the latency of the candidate and
-// list loads, which the L1/L2 serve (neighbouring lanes read neighbouring
-// cells).
+// grid-stride loop.  Apart from the builds' coherent waves, no LDS and no
+// barriers: every lane is independent, so the kernels hold many waves per
+// SIMD to hide the latency of the candidate and list loads, which the L1/L2
+// serve (neighbouring lanes read neighbouring cells).
 //  * Build: the lane walks the active set of its particle -- the (2R+1)^3
 //    cells around its own cell (paper Sec. 2.3: local vs active particles) --
 //    in a fixed order (dz, dy, then the row's cells along x, wrapped part
 //    first) and appends every candidate within its list radius to its list
 //    (entry k of particle p at list[k n + p], so that a wave's k-th entries
-//    are one contiguous 256-byte run).
+//    are one contiguous 256-byte run).  A wave whose particles share one
+//    dense cell walks that cell's window once for all of them, staging the
+//    candidates in LDS (walk_wave).
 //  * Evaluation: the lane walks its list in order, so every pair is evaluated
 //    with no divergence between lanes other than list lengths.
 //  * Density: one list (radius 2 h_l, h_l = min(h_cap, (1 + 1/16) h_0)) serves
